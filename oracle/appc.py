@@ -1,0 +1,108 @@
+"""Work distributions from reaction-coordinate distributions (App. C) -- TEST INFRASTRUCTURE ONLY.
+
+The paper builds the distribution Omega_j of the mechanical work W_mech needed
+to reach lambda_j by repeatedly folding in the distribution rho_{j-1} of x at
+the previous window: a work bin w of Omega_{j-1} combined with an x bin b of
+rho_{j-1} lands in bin floor(W/dW) with W = w dW + dW_{j-1}(x_b), and carries
+probability rho_{j-1}(b) Omega_{j-1}(w).
+
+Readings taken here (each also listed with its reason in the design notes):
+
+* the per-step increment is dlambda_i = lambda_{i+1} - lambda_i (not
+  (lambda_s - lambda_1)/s);
+* contributions are accumulated (+=) into a work bin, also for the first
+  step, since several x bins can land in one work bin;
+* floor is the mathematical floor; since w is an integer,
+  floor(w + dW/dW_bin) = w + floor(dW/dW_bin), so each x bin contributes an
+  integer shift s_b = floor(dW_{j-1}(x_b) / dW_bin) that is computed once;
+* the x representative of bin b is its centre xi_min + (b + 1/2) dxi;
+* the recursion runs to j = s, so the last window of the profile has a
+  distribution too; Omega_1 is the point mass at W = 0 (no step taken);
+* work outside [-M dW, (M+1) dW) is dropped and reported as lost mass.
+
+From Omega_j: dF^JE by Eq. 12 / App. B.5 (normalised average of
+exp(-beta W)), with W taken at the left bin edge w dW (each of the j-1 floors
+rounds down, so the true work lies in [w dW, (w + j - 1) dW)), and with the
+mid-point w dW + (j-1) dW/2; and the variance formula of Sec. IV A / App. C,
+sigma_W^2/Q + beta^2 sigma_W^4 / (2 (Q - 1)) with Q the number of non-zero bins.
+"""
+import numpy as np
+
+
+def paper_variance(sigma_w, Q, kT):
+    """Variance of dF^JE, sigma_W^2/Q + beta^2 sigma_W^4 / (2 (Q-1))."""
+    beta = 1.0 / kT
+    if Q <= 1:
+        return 0.0
+    return sigma_w ** 2 / Q + beta ** 2 * sigma_w ** 4 / (2.0 * (Q - 1))
+
+
+def bin_shifts(prob, window):
+    """Integer work-bin shift of every x bin for the step window -> window + 1."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    k = float(prob["k"])
+    K = int(prob["xi_nbins"])
+    x0 = float(prob["xi_min"]); dx = float(prob["xi_bin"]); dWb = float(prob["w_bin"])
+    xb = x0 + (np.arange(K) + 0.5) * dx
+    dW = 0.5 * k * ((xb - lam[window + 1]) ** 2 - (xb - lam[window]) ** 2)
+    return np.floor(dW / dWb).astype(np.int64)
+
+
+def work_distributions(prob, hist, n):
+    """Omega_j for j = 1..s and the quantities derived from them."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    s = len(lam)
+    kT = float(prob["kT"]); beta = 1.0 / kT
+    M = int(prob["w_half_bins"]); dWb = float(prob["w_bin"])
+    nb = 2 * M + 1
+    omega = np.zeros((s, nb))
+    omega[0, M] = 1.0                                  # W = 0 before any step
+    lost = np.zeros(s)
+    for j in range(1, s):
+        rho = hist[j - 1] / max(int(n[j - 1]), 1)        # probability per x bin
+        shifts = bin_shifts(prob, j - 1)
+        prev = omega[j - 1]
+        cur = omega[j]
+        for b in np.nonzero(rho)[0]:                   # the paper's loop over x bins
+            sb = int(shifts[b])
+            # every work bin w1 of Omega_{j-1} moves to w1 + sb (index space: +M offset)
+            lo = max(0, -sb); hi = min(nb, nb - sb)
+            if lo < hi:
+                cur[lo + sb:hi + sb] += rho[b] * prev[lo:hi]
+        lost[j] = 1.0 - cur.sum()
+    w = np.arange(-M, M + 1, dtype=np.float64)
+    je_left = np.full(s, np.nan); je_mid = np.full(s, np.nan)
+    var_paper = np.zeros(s); sigma_w = np.zeros(s); q_bins = np.zeros(s, dtype=np.int64)
+    for j in range(s):
+        om = omega[j]
+        tot = om.sum()
+        if tot <= 0:
+            continue
+        W_left = w * dWb
+        W_mid = W_left + 0.5 * j * dWb
+        # normalised exponential average (App. B.5)
+        je_left[j] = -kT * np.log(np.sum(om * np.exp(-beta * W_left)) / tot)
+        je_mid[j] = -kT * np.log(np.sum(om * np.exp(-beta * W_mid)) / tot)
+        mean_w = np.sum(om * W_left) / tot
+        sigma_w[j] = np.sqrt(max(np.sum(om * (W_left - mean_w) ** 2) / tot, 0.0))
+        q_bins[j] = np.count_nonzero(om)
+        var_paper[j] = paper_variance(sigma_w[j], q_bins[j], kT) if j > 0 else 0.0
+    return {"work_hist": omega, "work_lost": lost, "dF_je_hist": je_left, "dF_je_hist_mid": je_mid,
+            "sigma_w": sigma_w, "q_bins": q_bins, "dF_je_var_paper": var_paper}
+
+
+def product_form(prob, hist, n):
+    """The exact exponential average of the binned x distributions, without work binning:
+    -kT sum_{i<j} ln sum_b rho_i(b) exp(-beta dW_i(x_b)).  Used to pin the recursion."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    k = float(prob["k"]); kT = float(prob["kT"]); beta = 1.0 / kT
+    K = int(prob["xi_nbins"])
+    x0 = float(prob["xi_min"]); dx = float(prob["xi_bin"])
+    xb = x0 + (np.arange(K) + 0.5) * dx
+    out = np.zeros(len(lam))
+    for j in range(1, len(lam)):
+        i = j - 1
+        rho = hist[i] / max(int(n[i]), 1)
+        dW = 0.5 * k * ((xb - lam[i + 1]) ** 2 - (xb - lam[i]) ** 2)
+        out[j] = out[j - 1] - kT * np.log(np.sum(rho * np.exp(-beta * dW)) / np.sum(rho))
+    return out

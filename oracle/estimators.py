@@ -1,0 +1,182 @@
+"""Free-energy estimators of the parallel pulling protocol -- TEST INFRASTRUCTURE ONLY.
+
+Everything is computed in fp64 from the pooled xi samples of each window, by
+the definitions in the paper (arXiv:1105.4840):
+
+* step-wise work of the i-th step, the summand of Eq. 9:
+  dW_i(x) = k/2 [(x - lambda_{i+1})^2 - (x - lambda_i)^2];
+* JE along the windows, Eq. 12.  The windows are independent (Sec. II, the
+  remark that rho(W_mech) is proportional to the product of the rho(x_i)), so
+  <exp(-beta W_mech)> factorises into per-window averages and
+  dF^JE(lambda_j) = sum_{i<j} -kT ln < exp(-beta dW_i) >_i;
+* the alternative formula Eq. 14 and the Gaussian formula Eq. 13 (App. B.5),
+  read with the actual per-step increment dlambda_i = lambda_{i+1} - lambda_i;
+* the combined estimate (dF^JE + dF_fluct)/2 with uncertainty
+  (dF^JE - dF_fluct)/2 (Sec. IV B and IV D);
+* gamma_i^2 = k sigma_i^2 / kT (Sec. II, below Eq. 12);
+* jackknife standard errors over replica blocks, the JE variance formula of
+  Sec. IV A / App. C, Kish effective sample size and adjacent-window overlap.
+"""
+import numpy as np
+
+from . import appc
+
+
+def logsumexp(a):
+    """ln sum exp(a), by its definition with the maximum factored out."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.size == 0:
+        return -np.inf
+    m = np.max(a)
+    return m + np.log(np.sum(np.exp(a - m)))
+
+
+def step_work(x, lam_i, lam_next, k):
+    """Work of moving the restraint centre from lam_i to lam_next at fixed x (Eq. 9 summand)."""
+    return 0.5 * k * ((x - lam_next) ** 2 - (x - lam_i) ** 2)
+
+
+def block_of(replica, n_replicas, n_blocks):
+    """Jackknife block of a replica: contiguous blocks, block = floor(r B / R)."""
+    return (replica * n_blocks) // n_replicas
+
+
+def pooled(xi, kept, window, n_replicas, replicas=None):
+    """All kept samples of one window in replica order."""
+    rows = range(n_replicas) if replicas is None else replicas
+    base = window * n_replicas
+    parts = [xi[base + r, :kept[base + r]] for r in rows]
+    return np.concatenate(parts) if parts else np.zeros(0)
+
+
+def window_stats(samples, w, lam, k, kT):
+    """Per-window statistics used by the estimators."""
+    s = len(lam)
+    beta = 1.0 / kT
+    n = samples.size
+    out = {"n": n}
+    out["mean"] = np.mean(samples) if n else np.nan
+    out["var"] = np.var(samples, ddof=1) if n > 1 else np.nan
+    if w + 1 < s:
+        a = -beta * step_work(samples, lam[w], lam[w + 1], k)
+        out["lse_fwd"] = logsumexp(a)
+        out["lse_fwd2"] = logsumexp(2.0 * a)
+    else:
+        out["lse_fwd"] = out["lse_fwd2"] = np.nan
+    if w > 0:
+        ar = -beta * step_work(samples, lam[w], lam[w - 1], k)
+        out["lse_rev"] = logsumexp(ar)
+        out["lse_rev2"] = logsumexp(2.0 * ar)
+    else:
+        out["lse_rev"] = out["lse_rev2"] = np.nan
+    out["min"] = np.min(samples) if n else np.nan
+    out["max"] = np.max(samples) if n else np.nan
+    return out
+
+
+def profiles(stats, lam, k, kT):
+    """dF^JE, dF_fluct, dF^G, dF_com, unc and the reverse-direction JE profile."""
+    s = len(lam)
+    je = np.zeros(s); fl = np.zeros(s); g = np.zeros(s); rev = np.zeros(s)
+    for j in range(1, s):
+        i = j - 1
+        dl = lam[i + 1] - lam[i]
+        st = stats[i]
+        # Eq. 12 factorised over independent windows
+        je[j] = je[j - 1] - kT * (st["lse_fwd"] - np.log(st["n"]))
+        # Eq. 14 with the actual increment
+        fl[j] = fl[j - 1] + k * dl * (lam[i] - st["mean"])
+        # Eq. 13 / App. B.5 with the actual increment
+        gamma2 = k * st["var"] / kT
+        g[j] = g[j - 1] + k * dl * (lam[i] - st["mean"]) + 0.5 * k * dl * dl * (1.0 - gamma2)
+        # reverse perturbation from window i+1 to window i
+        sj = stats[j]
+        rev[j] = rev[j - 1] + kT * (sj["lse_rev"] - np.log(sj["n"]))
+    com = 0.5 * (je + fl)
+    unc = 0.5 * (je - fl)
+    return {"dF_je": je, "dF_fluct": fl, "dF_gauss": g, "dF_com": com, "dF_unc": unc, "dF_rev": rev}
+
+
+def histograms(xi, kept, prob):
+    """Counts of xi in K bins of width dxi from xi_min; bin b = floor((xi - xi_min)/dxi)."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    R = int(prob["n_replicas"])
+    K = int(prob["xi_nbins"])
+    x0 = float(prob["xi_min"]); dx = float(prob["xi_bin"])
+    hist = np.zeros((len(lam), K), dtype=np.int64)
+    uo = np.zeros((len(lam), 2), dtype=np.int64)
+    for w in range(len(lam)):
+        smp = pooled(xi, kept, w, R)
+        b = np.floor((smp - x0) / dx).astype(np.int64)
+        uo[w, 0] = np.count_nonzero(b < 0)
+        uo[w, 1] = np.count_nonzero(b >= K)
+        inr = b[(b >= 0) & (b < K)]
+        hist[w] = np.bincount(inr, minlength=K)
+    return hist, uo
+
+
+def estimate(prob, xi, kept, with_appc=True):
+    """All outputs of one protocol run, from the oracle's sample streams."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    k = float(prob["k"]); kT = float(prob["kT"])
+    s = len(lam)
+    R = int(prob["n_replicas"])
+    B = int(prob.get("n_blocks", 32))
+    B = max(1, min(B, R))
+
+    stats = [window_stats(pooled(xi, kept, w, R), w, lam, k, kT) for w in range(s)]
+    res = profiles(stats, lam, k, kT)
+
+    # jackknife over replica blocks (block b removed from every window)
+    blocks = [block_of(np.arange(R), R, B) == b for b in range(B)]
+    loo = {key: [] for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com")}
+    if B > 1:
+        for b in range(B):
+            keep_reps = np.nonzero(~blocks[b])[0]
+            st_b = [window_stats(pooled(xi, kept, w, R, keep_reps), w, lam, k, kT) for w in range(s)]
+            pr = profiles(st_b, lam, k, kT)
+            for key in loo:
+                loo[key].append(pr[key])
+        for key in loo:
+            th = np.array(loo[key])
+            res[key + "_se"] = np.sqrt((B - 1) / B * np.sum((th - th.mean(axis=0)) ** 2, axis=0))
+    else:
+        for key in loo:
+            res[key + "_se"] = np.full(s, np.nan)
+
+    n = np.array([st["n"] for st in stats], dtype=np.int64)
+    mean = np.array([st["mean"] for st in stats])
+    var = np.array([st["var"] for st in stats])
+    res["n_samples"] = n
+    res["xi_mean"] = mean
+    res["xi_std"] = np.sqrt(var)
+    res["gamma2"] = k * var / kT
+    res["lse_fwd"] = np.array([st["lse_fwd"] for st in stats])
+    res["lse_rev"] = np.array([st["lse_rev"] for st in stats])
+    res["xi_min_sample"] = np.array([st["min"] for st in stats])
+    res["xi_max_sample"] = np.array([st["max"] for st in stats])
+    # Kish effective sample fraction of the exponential weights, per forward step
+    res["kish_frac"] = np.array([np.exp(2 * st["lse_fwd"] - st["lse_fwd2"]) / st["n"]
+                                 if i + 1 < s else np.nan for i, st in enumerate(stats)])
+    res["n_blown_up"] = np.array([int(np.count_nonzero(
+        kept[w * R:(w + 1) * R] < (xi.shape[1] if xi.ndim == 2 else 0))) for w in range(s)])
+
+    hist, uo = histograms(xi, kept, prob)
+    res["xi_hist"] = hist
+    res["xi_under_over"] = uo
+
+    # overlap diagnostics for each adjacent pair (Sec. III, Sec. IV B, Sec. V)
+    dl = np.diff(lam)
+    sig = np.sqrt(var)
+    res["dlambda_over_sigma"] = np.abs(dl) / sig[:-1]
+    # distance from the centre of the distribution to its end in the pulling direction
+    reach = np.where(dl > 0, res["xi_max_sample"][:-1] - mean[:-1], mean[:-1] - res["xi_min_sample"][:-1])
+    res["reach"] = reach
+    res["dlambda_over_reach"] = np.abs(dl) / reach
+    res["criterion_ok"] = np.abs(dl) <= reach
+    rho = hist / np.maximum(n[:, None], 1)
+    res["overlap_ovl"] = np.sum(np.minimum(rho[:-1], rho[1:]), axis=1)
+
+    if with_appc and int(prob.get("w_half_bins", 0)) > 0:
+        res.update(appc.work_distributions(prob, hist, n))
+    return res

@@ -1,0 +1,360 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+Each test ties one part of the oracle to the paper's worked numbers, a closed
+form, a symmetry, an independent implementation or brute force, so that a
+dropped term, a wrong sign or index, or a transposed operand fails here.
+"""
+import json
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import ppp_inputs
+from oracle import appc, estimators, quadrature
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TORCH_INC = None
+try:
+    import torch.utils.cpp_extension as _ce
+    TORCH_INC = _ce.include_paths()[0]
+except Exception:  # pragma: no cover
+    pass
+
+# --------------------------------------------------------------------------- Philox
+
+_PHILOX_CPP = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+int main() {
+  unsigned long long seed, c0, c1, c2, c3;
+  while (scanf("%llu %llu %llu %llu %llu", &seed, &c0, &c1, &c2, &c3) == 5) {
+    // PyTorch's engine: key = seed, counter = (offset lo, offset hi, subseq lo, subseq hi)
+    at::philox_engine e(seed, c2 | (c3 << 32), c0 | (c1 << 32));
+    unsigned a = e(), b = e(), c = e(), d = e();
+    printf("%u %u %u %u\n", a, b, c, d);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.mark.skipif(TORCH_INC is None, reason="torch headers not found")
+def test_philox_matches_pytorch_engine():
+    """Philox4x32-10 (Salmon et al., SC'11) against PyTorch's independent header implementation."""
+    rng = np.random.default_rng(11)
+    cases = [(0, 0, 0, 0, 0), (0, 1, 0, 0, 0), (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 1)]
+    for _ in range(200):
+        cases.append((int(rng.integers(0, 2 ** 63)),) + tuple(int(x) for x in rng.integers(0, 2 ** 32, 4)))
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "p.cpp"); exe = os.path.join(d, "p")
+        open(src, "w").write(_PHILOX_CPP)
+        subprocess.run(["g++", "-std=c++17", "-O1", "-I", TORCH_INC, src, "-o", exe], check=True)
+        inp = "\n".join(" ".join(str(v) for v in c) for c in cases) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        seed = c[0]
+        mine = oracle.philox([seed & 0xFFFFFFFF, seed >> 32], list(c[1:]))
+        assert mine == [int(x) for x in line.split()], c
+
+
+def test_normals_statistics():
+    """Box-Muller normals: mean 0, variance 1, Gaussian tails (KS), no correlation between slots."""
+    from scipy import stats
+    z = np.array([oracle.normals4(5, g, n, 3, 0) for g in range(40) for n in range(250)])
+    assert abs(z.mean()) < 4.0 / np.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5.0 * np.sqrt(2.0 / z.size)
+    assert stats.kstest(z.ravel(), "norm").pvalue > 1e-3
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(4))) < 5.0 / np.sqrt(z.shape[0])
+
+
+# --------------------------------------------------------------------------- forces
+
+
+def _fd_forces(prob, r, lam, h=1e-6):
+    f = np.zeros_like(r)
+    for i in range(r.shape[0]):
+        for c in range(3):
+            rp = r.copy(); rm = r.copy()
+            rp[i, c] += h; rm[i, c] -= h
+            f[i, c] = -(oracle.chain_forces(prob, rp, lam)[0] - oracle.chain_forces(prob, rm, lam)[0]) / (2 * h)
+    return f
+
+
+@pytest.mark.parametrize("n_beads,rc_mode", [(10, 0), (13, 0), (7, 1)])
+def test_chain_forces_are_minus_energy_gradient(n_beads, rc_mode):
+    prob = ppp_inputs.chain_forcefield(n_beads)
+    prob.update({"k": 20.0, "rc_mode": rc_mode})
+    for r in ppp_inputs.random_chain_coords(n_beads, 3, seed=n_beads):
+        lam = 0.6 * (n_beads - 1)
+        _, _, f = oracle.chain_forces(prob, r, lam)
+        fd = _fd_forces(prob, r, lam)
+        assert np.max(np.abs(f - fd)) <= 1e-6 * max(1.0, np.max(np.abs(f)))
+
+
+def test_chain_force_special_cases():
+    base = ppp_inputs.chain_forcefield(4)
+    base.update({"k": 0.0})
+    # straight chain at bond length r0: no bond force, no angle force; LJ pair (0,3) at r = 3 > rc
+    r = np.array([[0, 0, 0], [0, 0, 1.0], [0, 0, 2.0], [0, 0, 3.0]])
+    e, parts, f = oracle.chain_forces(base, r, 0.0)
+    assert np.allclose(parts, 0.0, atol=1e-14) and np.allclose(f, 0.0, atol=1e-12)
+    # the only LJ pair (0,3) at the LJ minimum 2^(1/6) sigma: zero LJ force, energy -eps - U(rc)
+    rmin = 2.0 ** (1.0 / 6.0)
+    prob = dict(base, k_bond=0.0, k_angle=0.0)
+    r = np.array([[0, 0, 0], [0.3, 0.1, 0.2], [0.7, -0.2, 0.1], [rmin, 0, 0]])
+    e, parts, f = oracle.chain_forces(prob, r, 0.0)
+    u_rc = 4.0 * (2.5 ** -12 - 2.5 ** -6)
+    assert abs(parts[2] - (-1.0 - u_rc)) < 1e-13
+    assert np.allclose(f[0], 0.0, atol=1e-12) and np.allclose(f[3], 0.0, atol=1e-12)
+    # at r = sigma the LJ energy is 0 - U(rc); beyond the cutoff it is exactly 0
+    r[3] = [1.0, 0, 0]
+    assert abs(oracle.chain_forces(prob, r, 0.0)[1][2] - (-u_rc)) < 1e-13
+    r[3] = [2.6, 0, 0]
+    assert oracle.chain_forces(prob, r, 0.0)[1][2] == 0.0
+    # restraint: energy k/2 (xi - lam)^2 and force -k (xi - lam) along r_{N-1}
+    prob = dict(base, k=7.0, k_bond=0.0, k_angle=0.0, lj_eps=0.0)
+    r = np.array([[0, 0, 0], [0, 0, 1.0], [0, 1.0, 1.0], [3.0, 4.0, 0.0]])
+    e, parts, f = oracle.chain_forces(prob, r, 2.0)
+    assert abs(parts[3] - 0.5 * 7.0 * 9.0) < 1e-13
+    assert np.allclose(f[3], -7.0 * 3.0 * np.array([0.6, 0.8, 0.0]), atol=1e-13)
+    # angle: right angle between bonds gives k_theta (1 - 0)
+    prob = dict(base, k=0.0, k_bond=0.0, lj_eps=0.0)
+    r = np.array([[0, 0, 0], [1.0, 0, 0], [1.0, 1.0, 0], [1.0, 1.0, 1.0]])
+    assert abs(oracle.chain_forces(prob, r, 0.0)[1][1] - 2 * 5.0) < 1e-13
+
+
+def test_default_helix_geometry():
+    r = oracle.default_helix(10)
+    b = np.linalg.norm(np.diff(r, axis=0), axis=1)
+    assert np.allclose(b, 1.0, atol=1e-13)
+    assert np.allclose(r[0], 0.0)
+    d3 = np.linalg.norm(r[3:] - r[:-3], axis=1)
+    assert d3.min() > 1.3                      # no Lennard-Jones overlap in the start state
+    assert abs(r[-1, 2] - 0.395 * 9) < 1e-12
+
+
+def test_pot1d_force():
+    prob = ppp_inputs.config_1d()
+    for x in [-1.7, -0.3, 0.0, 0.9, 1.4]:
+        e, F = oracle.pot1d(prob, x, 0.45)
+        h = 1e-6
+        fd = -(oracle.pot1d(prob, x + h, 0.45)[0] - oracle.pot1d(prob, x - h, 0.45)[0]) / (2 * h)
+        assert abs(F - fd) < 1e-6 * max(1, abs(F))
+        assert abs(e - (5 * (x * x - 1) ** 2 + 25 * (x - 0.45) ** 2)) < 1e-12
+
+
+# --------------------------------------------------------------------------- integrators
+
+
+def _harmonic_var(integrator, dt, K=30.0, kT=1.0, R=256, steps=6000):
+    prob = ppp_inputs.config_harmonic_1d(kappa=K - 10.0, k=10.0, n_replicas=R, n_steps=steps, seed=4)
+    prob.update({"lambda": [0.0, 0.5], "dt": dt, "integrator_1d": integrator, "init_coords": [0.0],
+                 "n_equil": 1000, "sample_every": 20})
+    xi, kept, _ = oracle.run(prob)
+    x = xi[:R]                                  # window lambda = 0
+    return x.var(axis=1, ddof=1).mean(), x.var(axis=1, ddof=1).std() / np.sqrt(R)
+
+
+def test_lm_stationary_variance_is_exact_for_harmonic():
+    """Leimkuhler-Matthews keeps the exact stationary variance kT/K of a harmonic well."""
+    K, dt = 30.0, 0.02                        # K dt = 0.6: a large step makes any bias visible
+    v, se = _harmonic_var(0, dt, K)
+    assert abs(v - 1.0 / K) < 4 * se + 1e-4
+
+
+def test_em_stationary_variance_closed_form():
+    """Euler-Maruyama on a harmonic well: var = kT / (K (1 - K dt / 2))."""
+    K, dt = 30.0, 0.02
+    v, se = _harmonic_var(1, dt, K)
+    assert abs(v - 1.0 / (K * (1 - K * dt / 2))) < 4 * se + 1e-4
+    assert v - 1.0 / K > 8 * se               # and it is visibly biased
+
+
+def test_trajectory_matches_run_samples():
+    """The parity hook replays the same replica as the full run."""
+    prob = ppp_inputs.config_chain_small(6, n_replicas=4, n_steps=60)
+    prob.update({"n_equil": 0, "sample_every": 1})
+    xi, kept, _ = oracle.run(prob)
+    tr = oracle.trajectory(prob, 2, 3, 60)
+    r = tr[:, -3:]
+    d = np.linalg.norm(r, axis=1)
+    assert np.allclose(d[1:], xi[2 * 4 + 3, :60], rtol=0, atol=1e-13)
+
+
+def test_nan_start_freezes_replica():
+    prob = ppp_inputs.config_1d(n_replicas=4, n_steps=200)
+    prob["init_coords"] = [float("nan")]
+    xi, kept, _ = oracle.run(prob)
+    assert np.all(kept == 0)
+    res = estimators.estimate(prob, xi, kept, with_appc=False)
+    assert np.all(res["n_blown_up"] == 4)
+
+
+# --------------------------------------------------------------------------- quadrature
+
+
+def test_quadrature_reproduces_harmonic_closed_form():
+    kappa, k, kT = 4.0, 20.0, 1.3
+    lam = np.linspace(-1, 1, 7)
+    F, mu, var = quadrature.restrained_1d(lambda x: 0.5 * kappa * x * x, lam, k, kT)
+    Fc, muc, varc = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    assert np.allclose(F - F[3], Fc - Fc[3], atol=1e-11)
+    assert np.allclose(mu, muc, atol=1e-12) and np.allclose(var, varc, rtol=1e-10)
+
+
+def test_double_well_profile_symmetry():
+    """U(x) = U(-x) and a symmetric window set: F(lambda) = F(-lambda), so dF(lambda_21) = 0."""
+    p = ppp_inputs.config_1d()
+    F, mu, var = quadrature.restrained_1d(quadrature.double_well(), p["lambda"], p["k"], p["kT"])
+    assert np.allclose(F, F[::-1], atol=1e-11)
+    assert np.allclose(mu, -mu[::-1], atol=1e-12)
+
+
+def test_chain2_quadrature_reduces_to_closed_form_without_bond():
+    """N = 2, k_b = 0: xi = |r| with density r^2 exp(-beta k/2 (r - lam)^2); for lam >> sd
+    F(lam) - F(lam') = -2 kT ln(lam/lam') up to O(sd^2/lam^2)."""
+    k, kT = 400.0, 1.0
+    F, mu, var = quadrature.chain2([20.0, 40.0], k, kT, 0.0, 1.0, lo=1e-3, hi=45.0, n_panels=4000)
+    exact = -2 * kT * np.log(40.0 / 20.0) - kT * (np.log(1 + kT / (k * 40 ** 2)) - np.log(1 + kT / (k * 20 ** 2)))
+    assert abs((F[1] - F[0]) - exact) < 1e-8
+
+
+# --------------------------------------------------------------------------- estimators
+
+
+def test_step_work_is_eq9_summand():
+    x = np.array([0.3, 1.7]); li, ln, k = 0.5, 1.25, 7.2
+    # Eq. 9: k/2 (lambda_{i+1} - lambda_i)(lambda_{i+1} + lambda_i - 2 x_i)
+    assert np.allclose(estimators.step_work(x, li, ln, k), 0.5 * k * (ln - li) * (ln + li - 2 * x))
+
+
+def test_gaussian_windows_make_eq13_exact():
+    """Exactly Gaussian xi (restrained harmonic oscillator) with known moments:
+    Eq. 13 reproduces the exact profile for any dlambda; Eq. 14 misses
+    sum k dlambda^2/2 (1 - k/(kappa+k)); JE is unbiased."""
+    kappa, k, kT = 4.0, 20.0, 1.0
+    lam = np.linspace(-1, 1, 11)
+    Fc, mu, var = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    fl, g = quadrature.estimator_expectations(lam, mu, var, k, kT)
+    exact = Fc - Fc[0]
+    assert np.allclose(g, exact, atol=1e-12)
+    dl = np.diff(lam)
+    miss = np.concatenate([[0], np.cumsum(0.5 * k * dl ** 2 * (1 - k / (kappa + k)))])
+    assert np.allclose(fl, exact - miss, atol=1e-12)
+
+
+def test_oracle_je_matches_harmonic_closed_form():
+    p = ppp_inputs.config_harmonic_1d(n_replicas=256, n_steps=8000)
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    Fc, mu, var = quadrature.harmonic_closed_form(p["pot_kappa"], p["k"], p["kT"], p["lambda"])
+    exact = Fc - Fc[0]
+    fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
+    for est, ref in (("dF_je", exact), ("dF_gauss", g), ("dF_fluct", fl)):
+        z = (r[est][-1] - ref[-1]) / r[est + "_se"][-1]
+        assert abs(z) < 3.5, (est, r[est][-1], ref[-1], r[est + "_se"][-1])
+    assert np.allclose(r["gamma2"], p["k"] / (p["k"] + p["pot_kappa"]), rtol=0.05)
+
+
+def test_oracle_je_matches_double_well_quadrature():
+    p = ppp_inputs.config_1d(n_replicas=256, n_steps=20000, seed=1)
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    F, mu, var = quadrature.restrained_1d(quadrature.double_well(), p["lambda"], p["k"], p["kT"])
+    exact = F - F[0]
+    z = (r["dF_je"] - exact)[1:] / r["dF_je_se"][1:]
+    assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 4.0
+    # dF_fluct is biased by construction (survey of the exact moments: about -2 kT at the end)
+    fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
+    assert abs((r["dF_fluct"][-1] - fl[-1]) / r["dF_fluct_se"][-1]) < 3.5
+    assert fl[-1] < -1.9
+
+
+@pytest.mark.parametrize("n_beads", [2, 3])
+def test_oracle_chain_je_matches_quadrature(n_beads):
+    """BAOAB chains with no Lennard-Jones pair: JE against exact radial (N=2) or 3-D (N=3) quadrature."""
+    p = ppp_inputs.config_chain_small(n_beads, n_replicas=128, n_steps=6000, n_windows=6)
+    p["lambda"] = list(np.linspace(0.6, 1.6, 6) if n_beads == 2 else np.linspace(1.2, 2.2, 6))
+    p["n_blocks"] = 16
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    if n_beads == 2:
+        F, mu, var = quadrature.chain2(p["lambda"], p["k"], p["kT"], p["k_bond"], p["r0"])
+    else:
+        F, mu, var = quadrature.chain3(p["lambda"], p["k"], p["kT"], p["k_bond"], p["r0"], p["k_angle"])
+    exact = F - F[0]
+    z = (r["dF_je"] - exact)[1:] / r["dF_je_se"][1:]
+    assert np.max(np.abs(z)) < 3.5, z
+    zm = (r["xi_mean"] - mu) / (r["xi_std"] / np.sqrt(r["n_samples"] / 20.0))
+    assert np.max(np.abs(zm)) < 4.0
+
+
+def test_kish_and_lse_definitions():
+    a = np.zeros(10)
+    assert abs(estimators.logsumexp(a) - np.log(10)) < 1e-15
+    assert abs(estimators.logsumexp(np.array([1000.0, 1000.0])) - (1000 + np.log(2))) < 1e-12
+    assert estimators.logsumexp(np.zeros(0)) == -np.inf
+
+
+# --------------------------------------------------------------------------- App. C
+
+
+def test_paper_variance_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "je_variance_example.json")))
+    kT = g["boltzmann_kcal_per_mol_K"] * g["temperature_K"]
+    var = appc.paper_variance(g["sigma_w_kcal_per_mol"], g["Q"], kT)
+    assert abs(var - g["paper_variance_approx"]) < 0.05
+    assert abs(np.sqrt(var) - g["paper_sd_approx"]) < 0.05
+    assert abs(var - 0.7085) < 5e-4
+
+
+def _tiny_problem():
+    p = {"lambda": [0.0, 0.4, 1.0], "k": 3.0, "kT": 0.8, "xi_min": -0.5, "xi_bin": 0.25,
+         "xi_nbins": 5, "w_bin": 0.05, "w_half_bins": 200}
+    hist = np.array([[1, 3, 0, 2, 1], [0, 2, 2, 1, 4], [5, 0, 0, 0, 1]])
+    return p, hist, hist.sum(axis=1)
+
+
+def test_appc_brute_force_tiny():
+    """Enumerate every combination of x bins of windows 1 and 2: the work bin is
+    floor(dW_1(x_a)/dW) + floor(dW_2(x_b)/dW) and its probability rho_1(a) rho_2(b)."""
+    p, hist, n = _tiny_problem()
+    out = appc.work_distributions(p, hist, n)
+    M = p["w_half_bins"]; dWb = p["w_bin"]
+    lam = p["lambda"]; k = p["k"]
+    xb = p["xi_min"] + (np.arange(5) + 0.5) * p["xi_bin"]
+    ref2 = np.zeros(2 * M + 1); ref3 = np.zeros(2 * M + 1)
+    for a in range(5):
+        wa = int(np.floor(0.5 * k * ((xb[a] - lam[1]) ** 2 - (xb[a] - lam[0]) ** 2) / dWb))
+        ref2[M + wa] += hist[0, a] / n[0]
+        for b in range(5):
+            wb = int(np.floor(0.5 * k * ((xb[b] - lam[2]) ** 2 - (xb[b] - lam[1]) ** 2) / dWb))
+            ref3[M + wa + wb] += hist[0, a] / n[0] * hist[1, b] / n[1]
+    assert np.allclose(out["work_hist"][1], ref2, atol=1e-15)
+    assert np.allclose(out["work_hist"][2], ref3, atol=1e-15)
+    assert out["work_hist"][0, M] == 1.0
+
+
+def test_appc_bounds_against_product_form():
+    """Each of the j-1 floors rounds the work down by less than one bin, so
+    dF_left <= dF_product <= dF_left + (j-1) dW, with dF_product the exact
+    exponential average of the binned x distributions."""
+    p = ppp_inputs.config_1d(n_replicas=64, n_steps=4000, seed=2)
+    xi, kept, _ = oracle.run(p)
+    hist, _ = estimators.histograms(xi, kept, p)
+    n = np.array([kept[w * 64:(w + 1) * 64].sum() for w in range(21)])
+    out = appc.work_distributions(p, hist, n)
+    prod = appc.product_form(p, hist, n)
+    j = np.arange(21)
+    assert np.all(out["dF_je_hist"] <= prod + 1e-9)
+    assert np.all(prod <= out["dF_je_hist"] + j * p["w_bin"] + 1e-9)
+    assert np.max(np.abs(out["work_lost"])) < 1e-12
+    # and against the unbinned JE: x binning moves each step's work by at most k |dl| dxi / 2
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    tol = np.cumsum(np.concatenate([[0], p["k"] * np.abs(np.diff(p["lambda"])) * p["xi_bin"] / 2]))
+    assert np.all(np.abs(prod - r["dF_je"]) <= tol + 1e-9)
