@@ -1,0 +1,137 @@
+// Device building blocks for gfx950: counter-based noise, log-sum-exp
+// accumulation and cross-lane data movement within a replica's lane group.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppp_internal.hpp"
+
+namespace ppp {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4x32 Philox S-box; the key advances by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
+        uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Four standard normals per Philox block by Box-Muller, in the requested
+// precision.  fp64: u = (r + 1/2) 2^-32 (exact); fp32: u = (r>>9 + 1/2) 2^-23
+// (exact in fp32, hardware log2/sin/cos, whose argument is in turns).
+template <typename T> struct Normal4;
+
+template <> struct Normal4<double> {
+    __device__ __forceinline__ static void get(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, double z[4]) {
+        U4 r = philox(seed, c0, c1, c2, c3);
+        const double scale = 1.0 / 4294967296.0;
+        const double two_pi = 6.283185307179586476925286766559;
+        double ua = ((double)r.x + 0.5) * scale, ub = ((double)r.y + 0.5) * scale;
+        double uc = ((double)r.z + 0.5) * scale, ud = ((double)r.w + 0.5) * scale;
+        double ra = sqrt(-2.0 * log(ua)), rc = sqrt(-2.0 * log(uc));
+        z[0] = ra * cos(two_pi * ub); z[1] = ra * sin(two_pi * ub);
+        z[2] = rc * cos(two_pi * ud); z[3] = rc * sin(two_pi * ud);
+    }
+};
+
+template <> struct Normal4<float> {
+    __device__ __forceinline__ static void get(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, float z[4]) {
+        U4 r = philox(seed, c0, c1, c2, c3);
+        const float scale = 1.0f / 8388608.0f;      // 2^-23
+        const float m2ln2 = -2.0f * 0.69314718055994531f;
+        float ua = ((float)(r.x >> 9) + 0.5f) * scale, ub = ((float)(r.y >> 9) + 0.5f) * scale;
+        float uc = ((float)(r.z >> 9) + 0.5f) * scale, ud = ((float)(r.w >> 9) + 0.5f) * scale;
+        float ra = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
+        float rc = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(uc));
+        z[0] = ra * __builtin_amdgcn_cosf(ub); z[1] = ra * __builtin_amdgcn_sinf(ub);
+        z[2] = rc * __builtin_amdgcn_cosf(ud); z[3] = rc * __builtin_amdgcn_sinf(ud);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Reciprocal in the working precision: the hardware approximation in fp32,
+// the IEEE quotient in fp64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+
+// ---------------------------------------------------------------------------
+// Running log-sum-exp (m, S): ln sum_k exp(a_k) = m + ln S.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lse_push(double &m, double &S, double a) {
+    if (a > m) { S = S * exp(m - a) + 1.0; m = a; }
+    else { S += exp(a - m); }
+}
+__device__ __forceinline__ void lse_merge(double &m, double &S, double m2, double S2) {
+    if (S2 == 0.0) return;
+    if (S == 0.0) { m = m2; S = S2; return; }
+    double M = fmax(m, m2);
+    S = S * exp(m - M) + S2 * exp(m2 - M);
+    m = M;
+}
+__device__ __forceinline__ double lse_value(double m, double S) {
+    return S > 0.0 ? m + log(S) : -INFINITY;
+}
+
+// Merge record b into record a (fixed field semantics, see AccField).
+__device__ __forceinline__ void acc_merge(double *a, const double *b) {
+    a[A_N] += b[A_N]; a[A_S1] += b[A_S1]; a[A_S2] += b[A_S2];
+    a[A_XMIN] = fmin(a[A_XMIN], b[A_XMIN]); a[A_XMAX] = fmax(a[A_XMAX], b[A_XMAX]);
+    lse_merge(a[A_MF], a[A_SF], b[A_MF], b[A_SF]);
+    lse_merge(a[A_MF2], a[A_SF2], b[A_MF2], b[A_SF2]);
+    lse_merge(a[A_MR], a[A_SR], b[A_MR], b[A_SR]);
+    lse_merge(a[A_MR2], a[A_SR2], b[A_MR2], b[A_SR2]);
+    a[A_UNDER] += b[A_UNDER]; a[A_OVER] += b[A_OVER]; a[A_BLOWN] += b[A_BLOWN];
+}
+__device__ __forceinline__ void acc_empty(double *a) {
+    for (int f = 0; f < A_NFIELDS; ++f) a[f] = 0.0;
+    a[A_XMIN] = INFINITY; a[A_XMAX] = -INFINITY;
+    a[A_MF] = a[A_MF2] = a[A_MR] = a[A_MR2] = -INFINITY;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves inside a group of G consecutive lanes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float pull_f(int src_lane, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double pull_f(int src_lane, double v) {
+    int2 w = *reinterpret_cast<int2 *>(&v);
+    w.x = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.x);
+    w.y = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.y);
+    return *reinterpret_cast<double *>(&w);
+}
+__device__ __forceinline__ int pull_i(int src_lane, int v) {
+    return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
+}
+// push: lane dst_lane receives v (every destination must be written by exactly one lane)
+__device__ __forceinline__ float push_f(int dst_lane, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_permute(dst_lane << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double push_f(int dst_lane, double v) {
+    int2 w = *reinterpret_cast<int2 *>(&v);
+    w.x = __builtin_amdgcn_ds_permute(dst_lane << 2, w.x);
+    w.y = __builtin_amdgcn_ds_permute(dst_lane << 2, w.y);
+    return *reinterpret_cast<double *>(&w);
+}
+
+}  // namespace ppp

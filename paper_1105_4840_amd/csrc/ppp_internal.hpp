@@ -1,0 +1,84 @@
+// Internal layout shared by the HIP kernels and the host runtime of libppp.
+// Nothing here is part of the C ABI (include/ppp.h).
+#pragma once
+#include <stdint.h>
+
+namespace ppp {
+
+// Per-replica accumulator record (fp64), also the per-(window, block) and
+// per-window record after reduction.
+enum AccField : int {
+    A_N = 0,      // number of samples
+    A_S1,         // sum (xi - lambda_i)
+    A_S2,         // sum (xi - lambda_i)^2
+    A_XMIN,       // smallest sample
+    A_XMAX,       // largest sample
+    A_MF, A_SF,   // running log-sum-exp of a = -beta dW_i (forward): max and scaled sum
+    A_MF2, A_SF2, // same for 2a
+    A_MR, A_SR,   // reverse perturbation lambda_i -> lambda_{i-1}
+    A_MR2, A_SR2,
+    A_UNDER, A_OVER,
+    A_BLOWN,      // 1 if the replica was frozen
+    A_NFIELDS
+};
+
+// Output arrays of one problem (each [s] doubles), in this order.
+enum OutField : int {
+    O_DF_JE = 0, O_DF_JE_SE, O_DF_FLUCT, O_DF_FLUCT_SE, O_DF_GAUSS, O_DF_GAUSS_SE,
+    O_DF_COM, O_DF_COM_SE, O_DF_UNC, O_DF_REV,
+    O_DF_JE_HIST, O_DF_JE_HIST_MID, O_VAR_PAPER, O_SIGMA_W, O_Q_BINS, O_WORK_LOST,
+    O_XI_MEAN, O_XI_STD, O_GAMMA2, O_XI_MINS, O_XI_MAXS, O_LSE_FWD, O_LSE_REV,
+    O_N_SAMPLES, O_N_BLOWN, O_UNDER, O_OVER,
+    O_KISH, O_OVL, O_DL_SIGMA, O_DL_REACH, O_CRIT,
+    O_NFIELDS
+};
+
+// Jackknife leave-one-out profiles stored per block: JE, fluct, gauss, com.
+constexpr int JK_FIELDS = 4;
+
+struct DevProblem {
+    // model
+    int32_t model;          // 0: 1-D, 1: chain
+    int32_t precision;      // 0: fp32 forces, 1: fp64
+    int32_t pot_kind, integrator_1d;
+    int32_t n_beads, n_pad, rc_mode;
+    int32_t n_windows, n_replicas, n_blocks;
+    int32_t xi_nbins, w_half_bins;
+    int32_t sample_every;
+    int32_t variant_lanes, variant_beads;   // chain kernel shape (G lanes x B beads per lane)
+    int32_t pad0;
+    int64_t n_steps, n_equil, n_pull;
+    uint64_t seed;
+    double k, kT, beta, dt;
+    double pot_a, pot_b, pot_kappa, mobility;
+    double k_bond, r0, k_angle;
+    double lj_A, lj_B;      // force: f = inv_r2^4 (A inv_r2^3 - B) with A = 48 eps sig^12, B = 24 eps sig^6
+    double lj_eA, lj_eB;    // energy: inv_r2^3 (eA inv_r2^3 - eB) - ucut
+    double lj_ucut, rc2;
+    double mass, inv_mass, c1, c2sd, sd_v;   // BAOAB constants
+    double xi_min, xi_bin, w_bin, xi_bound, xi_start;
+    double fix_x, fix_y, fix_z;              // fixed bead 0
+    double pad_z0, pad_dz;                   // where padding beads are parked
+    // byte offsets of this problem's arrays inside the workspace
+    int64_t off_lambda;     // double [s]
+    int64_t off_init;       // double [3 N] (chain) or [1]
+    int64_t off_state;      // T [s R][6][n_pad] (chain) or T [s R][2] (1-D: x, eta)
+    int64_t off_acc;        // double [s R][A_NFIELDS]
+    int64_t off_hist;       // u64 [s][K]
+    int64_t off_blk;        // double [s][B][A_NFIELDS]
+    int64_t off_tot;        // double [s][A_NFIELDS]
+    int64_t off_jack;       // double [B][JK_FIELDS][s]
+    int64_t off_out;        // double [O_NFIELDS][s]
+    int64_t off_pairs_shift;// int32 [s][K]
+    int64_t off_pairs_prob; // double [s][K]
+    int64_t off_npairs;     // int32 [s]
+    int64_t off_omega;      // double [s][2M+1]
+};
+
+struct WorkItem {
+    int32_t prob, window, rep_begin, n_reps;
+};
+
+constexpr int WG = 256;  // threads per workgroup of the simulation kernels
+
+}  // namespace ppp

@@ -1,0 +1,381 @@
+// Reductions, estimators and work distributions of libppp (all fp64, fixed
+// merge order, so results do not depend on scheduling).
+//
+//   replica records --(per window, jackknife block)--> block records
+//   block records   --(per window)--> window totals
+//   window totals   --> Eq. 12 (JE, factorised over the independent windows),
+//                       Eq. 14 and Eq. 13 with the actual increments
+//                       lambda_{i+1} - lambda_i, combined estimate and its
+//                       uncertainty (Sec. IV B, IV D), reverse JE, gamma_i^2,
+//                       jackknife standard errors, Kish effective size,
+//                       overlap of adjacent histograms, the Sec. IV B criterion
+//   histograms      --> App. C work distributions Omega_j, dF^JE from them and
+//                       the variance formula of Sec. IV A.
+#include <hip/hip_runtime.h>
+
+#include "ppp_device.hpp"
+#include "ppp_launch.hpp"
+
+namespace ppp {
+
+__device__ __forceinline__ double *dptr(char *ws, int64_t off) { return reinterpret_cast<double *>(ws + off); }
+
+// ---------------------------------------------------------------------------
+__global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ ws, int *tickets, int n_tickets) {
+    const DevProblem &P = probs[blockIdx.y];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
+    const int64_t nh = (int64_t)P.n_windows * P.xi_nbins;
+    for (int64_t i = tid; i < nh; i += stride) hist[i] = 0ull;
+    if (P.w_half_bins > 0) {
+        double *om = dptr(ws, P.off_omega);
+        const int64_t nb = 2 * (int64_t)P.w_half_bins + 1;
+        const int64_t no = (int64_t)P.n_windows * nb;
+        for (int64_t i = tid; i < no; i += stride) om[i] = (i == P.w_half_bins) ? 1.0 : 0.0;  // Omega_1: W = 0
+    }
+    if (blockIdx.y == 0 && tid < n_tickets) tickets[tid] = 0;
+}
+
+hipError_t launch_init(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_k, int max_m,
+                       int *d_tickets, int n_tickets, hipStream_t stream) {
+    int64_t work = (int64_t)max_windows * max_k;
+    const int64_t wo = (int64_t)max_windows * (2 * (int64_t)max_m + 1);
+    if (wo > work) work = wo;
+    int nb = (int)((work + 255) / 256);
+    if (nb < 1) nb = 1;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_init, dim3(nb, n_probs), dim3(256), 0, stream, d_probs, ws, d_tickets, n_tickets);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One wave per (window, block): lanes merge strided replicas in order, then a
+// fixed butterfly-free tree (lane l takes lane l + off) down to lane 0.
+__global__ __launch_bounds__(64) void k_reduce_blocks(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+    const DevProblem &P = probs[blockIdx.y];
+    const int B = P.n_blocks, R = P.n_replicas;
+    const int wb = blockIdx.x;
+    if (wb >= P.n_windows * B) return;
+    const int w = wb / B, b = wb % B;
+    const int lo = (int)(((int64_t)b * R + B - 1) / B);
+    const int hi = (int)(((int64_t)(b + 1) * R + B - 1) / B);
+    const double *rec = dptr(ws, P.off_acc) + ((int64_t)w * R) * A_NFIELDS;
+    double a[A_NFIELDS];
+    acc_empty(a);
+    const int l = threadIdx.x;
+    for (int r = lo + l; r < hi; r += 64) acc_merge(a, rec + (int64_t)r * A_NFIELDS);
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o[A_NFIELDS];
+        for (int f = 0; f < A_NFIELDS; ++f) o[f] = pull_f(l + off < 64 ? l + off : l, a[f]);
+        if (l < off) acc_merge(a, o);
+    }
+    if (l == 0) {
+        double *dst = dptr(ws, P.off_blk) + (int64_t)wb * A_NFIELDS;
+        for (int f = 0; f < A_NFIELDS; ++f) dst[f] = a[f];
+    }
+}
+
+hipError_t launch_reduce(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_blocks,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_reduce_blocks, dim3(max_windows * max_blocks, n_probs), dim3(64), 0, stream, d_probs, ws);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+struct WinStat {
+    double n, mean, var, lse_f, lse_r;
+};
+__device__ __forceinline__ WinStat win_stat(const double *a, double lam) {
+    WinStat s;
+    s.n = a[A_N];
+    const double m1 = a[A_S1] / a[A_N];
+    s.mean = lam + m1;
+    s.var = (a[A_S2] - a[A_N] * m1 * m1) / (a[A_N] - 1.0);
+    s.lse_f = lse_value(a[A_MF], a[A_SF]);
+    s.lse_r = lse_value(a[A_MR], a[A_SR]);
+    return s;
+}
+
+// contributions of the step i -> i+1 to JE, fluct, gauss
+__device__ __forceinline__ void step_terms(const DevProblem &P, const WinStat &st, double li, double lj, double &je,
+                                           double &fl, double &ga) {
+    const double dl = lj - li;
+    je = -P.kT * (st.lse_f - log(st.n));
+    fl = P.k * dl * (li - st.mean);
+    const double gamma2 = P.k * st.var / P.kT;
+    ga = fl + 0.5 * P.k * dl * dl * (1.0 - gamma2);
+}
+
+__device__ double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off >= 1; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+    const DevProblem &P = probs[blockIdx.x];
+    __shared__ double sh[256];
+    const int s = P.n_windows, B = P.n_blocks, K = P.xi_nbins;
+    const int t = threadIdx.x;
+    const double *lam = dptr(ws, P.off_lambda);
+    const double *blk = dptr(ws, P.off_blk);
+    double *tot = dptr(ws, P.off_tot);
+    double *out = dptr(ws, P.off_out);
+    double *jack = dptr(ws, P.off_jack);
+    const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist);
+#define OUT(f, i) out[(int64_t)(f) * s + (i)]
+
+    // (a) window totals: blocks merged in block order
+    for (int w = t; w < s; w += blockDim.x) {
+        double a[A_NFIELDS];
+        acc_empty(a);
+        for (int b = 0; b < B; ++b) acc_merge(a, blk + ((int64_t)w * B + b) * A_NFIELDS);
+        for (int f = 0; f < A_NFIELDS; ++f) tot[(int64_t)w * A_NFIELDS + f] = a[f];
+    }
+    __syncthreads();
+    // (b) per-window statistics
+    for (int w = t; w < s; w += blockDim.x) {
+        const double *a = tot + (int64_t)w * A_NFIELDS;
+        const WinStat st = win_stat(a, lam[w]);
+        OUT(O_XI_MEAN, w) = st.mean;
+        OUT(O_XI_STD, w) = sqrt(st.var);
+        OUT(O_GAMMA2, w) = P.k * st.var / P.kT;
+        OUT(O_XI_MINS, w) = a[A_XMIN];
+        OUT(O_XI_MAXS, w) = a[A_XMAX];
+        OUT(O_LSE_FWD, w) = w + 1 < s ? st.lse_f : NAN;
+        OUT(O_LSE_REV, w) = w > 0 ? st.lse_r : NAN;
+        OUT(O_N_SAMPLES, w) = a[A_N];
+        OUT(O_N_BLOWN, w) = a[A_BLOWN];
+        OUT(O_UNDER, w) = a[A_UNDER];
+        OUT(O_OVER, w) = a[A_OVER];
+        if (w + 1 < s) {
+            const double dl = lam[w + 1] - lam[w];
+            OUT(O_KISH, w) = exp(2.0 * st.lse_f - lse_value(a[A_MF2], a[A_SF2])) / st.n;
+            OUT(O_DL_SIGMA, w) = fabs(dl) / sqrt(st.var);
+            const double reach = dl > 0 ? a[A_XMAX] - st.mean : st.mean - a[A_XMIN];
+            OUT(O_DL_REACH, w) = fabs(dl) / reach;
+            OUT(O_CRIT, w) = fabs(dl) <= reach ? 1.0 : 0.0;
+        } else {
+            OUT(O_KISH, w) = NAN; OUT(O_DL_SIGMA, w) = NAN; OUT(O_DL_REACH, w) = NAN; OUT(O_CRIT, w) = NAN;
+        }
+    }
+    __syncthreads();
+    // (c) profiles: prefix sums over the steps
+    if (t == 0) {
+        double je = 0, fl = 0, ga = 0, rev = 0;
+        OUT(O_DF_JE, 0) = 0; OUT(O_DF_FLUCT, 0) = 0; OUT(O_DF_GAUSS, 0) = 0; OUT(O_DF_REV, 0) = 0;
+        for (int j = 1; j < s; ++j) {
+            const WinStat st = win_stat(tot + (int64_t)(j - 1) * A_NFIELDS, lam[j - 1]);
+            double dje, dfl, dga;
+            step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
+            je += dje; fl += dfl; ga += dga;
+            const WinStat sj = win_stat(tot + (int64_t)j * A_NFIELDS, lam[j]);
+            rev += P.kT * (sj.lse_r - log(sj.n));
+            OUT(O_DF_JE, j) = je; OUT(O_DF_FLUCT, j) = fl; OUT(O_DF_GAUSS, j) = ga; OUT(O_DF_REV, j) = rev;
+        }
+        for (int j = 0; j < s; ++j) {
+            OUT(O_DF_COM, j) = 0.5 * (OUT(O_DF_JE, j) + OUT(O_DF_FLUCT, j));
+            OUT(O_DF_UNC, j) = 0.5 * (OUT(O_DF_JE, j) - OUT(O_DF_FLUCT, j));
+        }
+    }
+    // (d) jackknife: block b removed from every window
+    if (B > 1) {
+        for (int b = t; b < B; b += blockDim.x) {
+            double je = 0, fl = 0, ga = 0;
+            double *jb = jack + (int64_t)b * JK_FIELDS * s;
+            jb[0 * s] = 0; jb[1 * s] = 0; jb[2 * s] = 0; jb[3 * s] = 0;
+            for (int j = 1; j < s; ++j) {
+                double a[A_NFIELDS];
+                acc_empty(a);
+                for (int c = 0; c < B; ++c)
+                    if (c != b) acc_merge(a, blk + ((int64_t)(j - 1) * B + c) * A_NFIELDS);
+                const WinStat st = win_stat(a, lam[j - 1]);
+                double dje, dfl, dga;
+                step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
+                je += dje; fl += dfl; ga += dga;
+                jb[0 * s + j] = je; jb[1 * s + j] = fl; jb[2 * s + j] = ga; jb[3 * s + j] = 0.5 * (je + fl);
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = t; j < s; j += blockDim.x) {
+        const int fields[JK_FIELDS] = {O_DF_JE_SE, O_DF_FLUCT_SE, O_DF_GAUSS_SE, O_DF_COM_SE};
+        for (int q = 0; q < JK_FIELDS; ++q) {
+            double se = NAN;
+            if (B > 1) {
+                double m = 0;
+                for (int b = 0; b < B; ++b) m += jack[((int64_t)b * JK_FIELDS + q) * s + j];
+                m /= B;
+                double ss = 0;
+                for (int b = 0; b < B; ++b) {
+                    const double d = jack[((int64_t)b * JK_FIELDS + q) * s + j] - m;
+                    ss += d * d;
+                }
+                se = sqrt((B - 1.0) / B * ss);
+            }
+            OUT(fields[q], j) = se;
+        }
+    }
+    // (e) overlap of adjacent histograms: sum_b min(rho_i(b), rho_{i+1}(b))
+    for (int i = 0; i + 1 < s; ++i) {
+        const double ni = tot[(int64_t)i * A_NFIELDS + A_N], nj = tot[(int64_t)(i + 1) * A_NFIELDS + A_N];
+        double part = 0;
+        for (int b = t; b < K; b += blockDim.x)
+            part += fmin((double)hist[(int64_t)i * K + b] / ni, (double)hist[(int64_t)(i + 1) * K + b] / nj);
+        const double ovl = block_sum(part, sh);
+        if (t == 0) OUT(O_OVL, i) = ovl;
+    }
+    if (t == 0) OUT(O_OVL, s - 1) = NAN;
+#undef OUT
+}
+
+hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, hipStream_t stream) {
+    hipLaunchKernelGGL(k_estimators, dim3(n_probs), dim3(256), 0, stream, d_probs, ws);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// App. C.  For the step i -> i+1, every non-empty x bin b of rho_i shifts the
+// work by s_b = floor(dW_i(x_b) / dW) bins (x_b the bin centre) and carries
+// probability rho_i(b); runs of equal shift are merged (s_b is monotone in b).
+__global__ void k_appc_pairs(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+#pragma clang fp contract(off)
+    const DevProblem &P = probs[blockIdx.y];
+    const int i = blockIdx.x;
+    if (P.w_half_bins <= 0 || i + 1 >= P.n_windows || threadIdx.x != 0) return;
+    const int K = P.xi_nbins;
+    const double *lam = dptr(ws, P.off_lambda);
+    const double *tot = dptr(ws, P.off_tot);
+    const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)i * K;
+    int *shift = reinterpret_cast<int *>(ws + P.off_pairs_shift) + (int64_t)i * K;
+    double *prob = dptr(ws, P.off_pairs_prob) + (int64_t)i * K;
+    const double n = tot[(int64_t)i * A_NFIELDS + A_N];
+    const double li = lam[i], lj = lam[i + 1];
+    int np = 0;
+    for (int b = 0; b < K; ++b) {
+        const unsigned long long c = hist[b];
+        if (c == 0ull) continue;
+        const double xb = P.xi_min + ((double)b + 0.5) * P.xi_bin;
+        const double dW = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li));
+        const double fs = floor(dW / P.w_bin);
+        const int sb = fs > 2.0e9 ? 2000000000 : (fs < -2.0e9 ? -2000000000 : (int)fs);
+        const double pb = (double)c / n;
+        if (np > 0 && shift[np - 1] == sb) prob[np - 1] += pb;
+        else { shift[np] = sb; prob[np] = pb; ++np; }
+    }
+    reinterpret_cast<int *>(ws + P.off_npairs)[i] = np;
+}
+
+// Omega_j(w) = sum_t prob_t Omega_{j-1}(w - shift_t), the folding step of App. C.
+__global__ __launch_bounds__(256) void k_appc_step(const DevProblem *__restrict__ probs, char *__restrict__ ws, int j) {
+    const DevProblem &P = probs[blockIdx.y];
+    if (P.w_half_bins <= 0 || j >= P.n_windows) return;
+    const int64_t nb = 2 * (int64_t)P.w_half_bins + 1;
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = reinterpret_cast<const int *>(ws + P.off_npairs)[j - 1];
+    const int *shift = reinterpret_cast<const int *>(ws + P.off_pairs_shift) + (int64_t)(j - 1) * P.xi_nbins;
+    const double *prob = dptr(ws, P.off_pairs_prob) + (int64_t)(j - 1) * P.xi_nbins;
+    const double *prev = dptr(ws, P.off_omega) + (int64_t)(j - 1) * nb;
+    double *cur = dptr(ws, P.off_omega) + (int64_t)j * nb;
+    __shared__ int s_shift[256];
+    __shared__ double s_prob[256];
+    double acc = 0.0;
+    for (int t0 = 0; t0 < np; t0 += 256) {
+        const int cnt = np - t0 < 256 ? np - t0 : 256;
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) { s_shift[threadIdx.x] = shift[t0 + threadIdx.x]; s_prob[threadIdx.x] = prob[t0 + threadIdx.x]; }
+        __syncthreads();
+        if (w < nb) {
+            for (int t = 0; t < cnt; ++t) {
+                const int64_t src = w - s_shift[t];
+                if (src >= 0 && src < nb) acc += s_prob[t] * prev[src];
+            }
+        }
+    }
+    if (w < nb) cur[w] = acc;
+}
+
+// Statistics of Omega_j: normalised exponential average (App. B.5), spread and
+// the number of non-empty bins, the JE variance formula of Sec. IV A.
+__global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+    const DevProblem &P = probs[blockIdx.y];
+    const int j = blockIdx.x;
+    __shared__ double sh[256];
+    const int s = P.n_windows;
+    if (P.w_half_bins <= 0 || j >= s) return;
+    const int M = P.w_half_bins;
+    const int64_t nb = 2 * (int64_t)M + 1;
+    const double *om = dptr(ws, P.off_omega) + (int64_t)j * nb;
+    double *out = dptr(ws, P.off_out);
+    const double beta = P.beta, dWb = P.w_bin;
+    const double shift_mid = 0.5 * (double)j * dWb;
+    double tot = 0, q = 0, mw = 0, emax = -INFINITY;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double o = om[b];
+        if (o != 0.0) {
+            const double W = (double)(b - M) * dWb;
+            tot += o; q += 1.0; mw += o * W;
+            emax = fmax(emax, -beta * W);
+        }
+    }
+    tot = block_sum(tot, sh);
+    q = block_sum(q, sh);
+    mw = block_sum(mw, sh);
+    // block max
+    sh[threadIdx.x] = emax;
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    emax = sh[0];
+    __syncthreads();
+    const double mean = mw / tot;
+    double sl = 0, sm = 0, vv = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double o = om[b];
+        if (o != 0.0) {
+            const double W = (double)(b - M) * dWb;
+            sl += o * exp(-beta * W - emax);
+            sm += o * exp(-beta * (W + shift_mid) - emax);
+            vv += o * (W - mean) * (W - mean);
+        }
+    }
+    sl = block_sum(sl, sh);
+    sm = block_sum(sm, sh);
+    vv = block_sum(vv, sh);
+    if (threadIdx.x == 0) {
+        const double kT = P.kT;
+        const double sig = sqrt(fmax(vv / tot, 0.0));
+        out[(int64_t)O_DF_JE_HIST * s + j] = tot > 0 ? -kT * (emax + log(sl / tot)) : NAN;
+        out[(int64_t)O_DF_JE_HIST_MID * s + j] = tot > 0 ? -kT * (emax + log(sm / tot)) : NAN;
+        out[(int64_t)O_SIGMA_W * s + j] = sig;
+        out[(int64_t)O_Q_BINS * s + j] = q;
+        out[(int64_t)O_WORK_LOST * s + j] = 1.0 - tot;
+        double var = 0.0;
+        if (j > 0 && q > 1.0) var = sig * sig / q + beta * beta * sig * sig * sig * sig / (2.0 * (q - 1.0));
+        out[(int64_t)O_VAR_PAPER * s + j] = var;
+    }
+}
+
+hipError_t launch_appc(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_m,
+                       hipStream_t stream) {
+    if (max_m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_appc_pairs, dim3(max_windows, n_probs), dim3(64), 0, stream, d_probs, ws);
+    const int64_t nb = 2 * (int64_t)max_m + 1;
+    const int grid = (int)((nb + 255) / 256);
+    for (int j = 1; j < max_windows; ++j)
+        hipLaunchKernelGGL(k_appc_step, dim3(grid, n_probs), dim3(256), 0, stream, d_probs, ws, j);
+    hipLaunchKernelGGL(k_appc_stats, dim3(max_windows, n_probs), dim3(256), 0, stream, d_probs, ws);
+    return hipGetLastError();
+}
+
+}  // namespace ppp

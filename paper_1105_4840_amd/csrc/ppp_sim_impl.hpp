@@ -1,0 +1,594 @@
+// Simulation kernels (device code, included by the shape translation units) of the parallel pulling protocol (Sec. III(ii)): many
+// independent restrained Langevin replicas per window lambda_i, all started
+// from the shared state x_o, each recording xi every sample_every steps after
+// n_equil and folding it straight into fp64 accumulators:
+//   n, sum(xi - lambda_i), sum(xi - lambda_i)^2, min, max, the histogram rho_i,
+//   and running log-sum-exp pairs of a = -beta dW_i (Eq. 9 summand) for the
+//   forward step and of the reverse step, each also for 2a (Kish size).
+//
+// Two kernels:
+//   * sim_1d: one lane per replica, overdamped dynamics of one coordinate.
+//   * sim_chain<T, G, B>: G consecutive lanes per replica (G in {1, 4, 16, 64}),
+//     B beads per lane in registers (lane g owns beads gB .. gB+B-1).  The
+//     Lennard-Jones sum uses each unique pair once (Newton's third law): the
+//     j-beads rotate one lane per round through the group together with an
+//     accumulator of their reaction forces, which finally is pushed back to
+//     the owning lane.  Bonded terms read a two-bead halo from the
+//     neighbouring lanes.  Nothing leaves registers inside the step loop
+//     except the per-sample histogram increment (one u64 atomic).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ppp_device.hpp"
+#include "ppp_launch.hpp"
+
+namespace ppp {
+
+__device__ __forceinline__ double centre_at(const DevProblem &P, double lam, int64_t n) {
+    if (P.n_pull <= 0 || n >= P.n_pull) return lam;
+    return P.xi_start + (lam - P.xi_start) * ((double)n / (double)P.n_pull);
+}
+
+__device__ __forceinline__ bool sample_now(const DevProblem &P, int64_t n) {
+    return n > P.n_equil && ((n - P.n_equil) % P.sample_every) == 0;
+}
+
+// Folds one sample xi of window w into the replica's accumulator.
+__device__ __forceinline__ void accumulate(const DevProblem &P, const double *lam, int w, double xi,
+                                           double *acc, unsigned long long *hist) {
+    const int s = P.n_windows;
+    const double d = xi - lam[w];
+    acc[A_N] += 1.0;
+    acc[A_S1] += d;
+    acc[A_S2] += d * d;
+    acc[A_XMIN] = fmin(acc[A_XMIN], xi);
+    acc[A_XMAX] = fmax(acc[A_XMAX], xi);
+    if (w + 1 < s) {
+        // a = -beta k/2 [(xi - lambda_{i+1})^2 - (xi - lambda_i)^2] = beta k dl (d - dl/2)
+        const double dl = lam[w + 1] - lam[w];
+        const double a = P.beta * P.k * dl * (d - 0.5 * dl);
+        lse_push(acc[A_MF], acc[A_SF], a);
+        lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
+    }
+    if (w > 0) {
+        const double dl = lam[w - 1] - lam[w];
+        const double a = P.beta * P.k * dl * (d - 0.5 * dl);
+        lse_push(acc[A_MR], acc[A_SR], a);
+        lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
+    }
+    const double fb = floor((xi - P.xi_min) / P.xi_bin);
+    if (fb < 0.0) acc[A_UNDER] += 1.0;
+    else if (fb >= (double)P.xi_nbins) acc[A_OVER] += 1.0;
+    else atomicAdd(hist + (int64_t)w * P.xi_nbins + (int64_t)fb, 1ull);
+}
+
+template <typename T> __device__ __forceinline__ T *state_ptr(char *ws, const DevProblem &P) {
+    return reinterpret_cast<T *>(ws + P.off_state);
+}
+
+// ===========================================================================
+// 1-D overdamped model: x_{n+1} = x_n + mu dt F(x_n) + sqrt(mu kT dt/2) (eta_n + eta_{n+1})
+// (Leimkuhler-Matthews) or + sqrt(2 mu kT dt) eta_{n+1} (Euler-Maruyama).
+// eta_n is component n mod 4 of the Philox block with counter (gid, n div 4, 0, 0).
+// ===========================================================================
+template <typename T>
+__device__ __forceinline__ T force_1d(const DevProblem &P, T x, T centre) {
+    T f;
+    if (P.pot_kind == 0) f = (T)(-4.0 * P.pot_a) * x * (x * x - (T)P.pot_b);
+    else f = (T)(-P.pot_kappa) * x;
+    return f - (T)P.k * (x - centre);
+}
+
+template <typename T>
+__global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
+                                             int n_items, char *__restrict__ ws, int64_t step_begin,
+                                             int64_t step_end, double *__restrict__ traj, int traj_rep) {
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    const WorkItem item = items[it];
+    const DevProblem &P = probs[item.prob];
+    const int w = item.window;
+    const int rep = item.rep_begin + (int)threadIdx.x;
+    if ((int)threadIdx.x >= item.n_reps) return;
+    const int64_t g = (int64_t)w * P.n_replicas + rep;
+    const uint32_t gid = (uint32_t)g;
+    const double *lam = reinterpret_cast<const double *>(ws + P.off_lambda);
+    double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + g * A_NFIELDS;
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
+    T *st = state_ptr<T>(ws, P) + g * 2;
+    const double lam_w = lam[w];
+    const double x_start = reinterpret_cast<const double *>(ws + P.off_init)[0];
+    const int64_t n_end = step_end < P.n_steps ? step_end : P.n_steps;
+
+    double acc[A_NFIELDS];
+    T x, eta_prev;
+    if (step_begin == 0) {
+        acc_empty(acc);
+        x = (T)x_start;
+        T z[4];
+        Normal4<T>::get(P.seed, gid, 0u, 0u, 0u, z);
+        eta_prev = z[0];
+    } else {
+        for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
+        x = st[0]; eta_prev = st[1];
+    }
+    const bool record = traj != nullptr && g == traj_rep;
+    if (record && step_begin == 0) traj[0] = (double)x;
+    const T mu_dt = (T)(P.mobility * P.dt);
+    const T amp = P.integrator_1d == 0 ? (T)sqrt(0.5 * P.mobility * P.kT * P.dt)
+                                       : (T)sqrt(2.0 * P.mobility * P.kT * P.dt);
+    bool alive = acc[A_BLOWN] == 0.0;
+    T z[4];
+    uint32_t zblock = 0xFFFFFFFFu;
+    for (int64_t n = step_begin + 1; n <= n_end && alive; ++n) {
+        const T F = force_1d<T>(P, x, (T)centre_at(P, lam_w, n - 1));
+        const uint32_t blk = (uint32_t)(n >> 2);
+        if (blk != zblock) { Normal4<T>::get(P.seed, gid, blk, 0u, 0u, z); zblock = blk; }
+        const T eta = z[n & 3];
+        if (P.integrator_1d == 0) x = x + mu_dt * F + amp * (eta_prev + eta);
+        else x = x + mu_dt * F + amp * eta;
+        eta_prev = eta;
+        if (record && n <= 100000) traj[n] = (double)x;
+        if (sample_now(P, n)) {
+            const double xi = (double)x;
+            if (!isfinite(xi) || fabs(xi) > P.xi_bound) { acc[A_BLOWN] = 1.0; alive = false; break; }
+            accumulate(P, lam, w, xi, acc, hist);
+        }
+    }
+    for (int f = 0; f < A_NFIELDS; ++f) acc_g[f] = acc[f];
+    st[0] = x; st[1] = eta_prev;
+}
+
+// ===========================================================================
+// Chain model.
+// ===========================================================================
+template <typename T, int G, int B, bool ENERGY>
+struct ChainForce {
+    static constexpr int HALO = G > 1 ? 2 : 0;
+    static constexpr int L = B + 2 * HALO;   // local window of beads around the owned ones
+
+    // Lennard-Jones between bead sets a (owned) and b; N3: also accumulate reaction on b.
+    template <bool N3, bool MASK>
+    __device__ __forceinline__ static void lj_block(const DevProblem &P, const T (&ax)[B], const T (&ay)[B],
+                                                    const T (&az)[B], const T (&bx)[B], const T (&by)[B],
+                                                    const T (&bz)[B], T (&fx)[B], T (&fy)[B], T (&fz)[B],
+                                                    T (&gx)[B], T (&gy)[B], T (&gz)[B], int ia0, int ib0,
+                                                    T lA, T lB, T rc2, double &e_lj) {
+#pragma unroll
+        for (int b1 = 0; b1 < B; ++b1) {
+#pragma unroll
+            for (int b2 = 0; b2 < B; ++b2) {
+                const T dx = ax[b1] - bx[b2], dy = ay[b1] - by[b2], dz = az[b1] - bz[b2];
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T ir2 = rcp_t(r2);
+                const T ir6 = ir2 * ir2 * ir2;
+                T f = ir6 * ir2 * (lA * ir6 - lB);
+                bool ok = r2 < rc2;
+                if (MASK) {
+                    const int dij = (ia0 + b1) - (ib0 + b2);
+                    ok = ok && (dij > 2 || dij < -2);
+                }
+                f = ok ? f : (T)0;
+                if (ENERGY && ok) e_lj += (double)(ir6 * ((T)P.lj_eA * ir6 - (T)P.lj_eB)) - P.lj_ucut;
+                fx[b1] += f * dx; fy[b1] += f * dy; fz[b1] += f * dz;
+                if (N3) { gx[b2] -= f * dx; gy[b2] -= f * dy; gz[b2] -= f * dz; }
+            }
+        }
+    }
+
+    // Forces on the owned beads at restraint centre `centre`.  lane g of group base `gbase`.
+    // e[0..3] = bond, angle, lj, restraint energy contributions of this lane (ENERGY only).
+    __device__ __forceinline__ static void compute(const DevProblem &P, int g, int gbase, T centre,
+                                                   const T (&px)[B], const T (&py)[B], const T (&pz)[B],
+                                                   T (&fx)[B], T (&fy)[B], T (&fz)[B], double *e) {
+        const int N = P.n_beads;
+        const int i0 = g * B;
+        const T lA = (T)P.lj_A, lB = (T)P.lj_B, rc2 = (T)P.rc2;
+        double e_lj = 0.0, e_bond = 0.0, e_ang = 0.0, e_res = 0.0;
+#pragma unroll
+        for (int b = 0; b < B; ++b) { fx[b] = 0; fy[b] = 0; fz[b] = 0; }
+
+        // ---- Lennard-Jones: pairs inside the lane (|i-j| > 2 by construction) ----
+#pragma unroll
+        for (int b1 = 0; b1 < B; ++b1) {
+#pragma unroll
+            for (int b2 = b1 + 3; b2 < B; ++b2) {
+                const T dx = px[b1] - px[b2], dy = py[b1] - py[b2], dz = pz[b1] - pz[b2];
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T ir2 = rcp_t(r2);
+                const T ir6 = ir2 * ir2 * ir2;
+                T f = ir6 * ir2 * (lA * ir6 - lB);
+                const bool ok = r2 < rc2;
+                f = ok ? f : (T)0;
+                if (ENERGY && ok) e_lj += (double)(ir6 * ((T)P.lj_eA * ir6 - (T)P.lj_eB)) - P.lj_ucut;
+                fx[b1] += f * dx; fy[b1] += f * dy; fz[b1] += f * dz;
+                fx[b2] -= f * dx; fy[b2] -= f * dy; fz[b2] -= f * dz;
+            }
+        }
+        // ---- Lennard-Jones between lanes: rotate the j-beads through the group ----
+        if constexpr (G > 1) {
+            T qx[B], qy[B], qz[B], gx[B], gy[B], gz[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) { qx[b] = px[b]; qy[b] = py[b]; qz[b] = pz[b]; gx[b] = 0; gy[b] = 0; gz[b] = 0; }
+            int jo = g;                 // lane that owns the beads now held in q
+            int jo_n3 = g;
+            const int src = gbase + ((g + G - 1) % G);
+#pragma unroll 1
+            for (int r = 1; r <= G / 2; ++r) {
+#pragma unroll
+                for (int b = 0; b < B; ++b) { qx[b] = pull_f(src, qx[b]); qy[b] = pull_f(src, qy[b]); qz[b] = pull_f(src, qz[b]); }
+                jo = pull_i(src, jo);
+                const bool n3 = r < G / 2;
+                if (n3 && r > 1) {
+#pragma unroll
+                    for (int b = 0; b < B; ++b) { gx[b] = pull_f(src, gx[b]); gy[b] = pull_f(src, gy[b]); gz[b] = pull_f(src, gz[b]); }
+                }
+                const int dl = g - jo;
+                const bool near = (dl == 1 || dl == -1);
+                const bool any_near = __ballot(near) != 0ull;
+                double e_r = 0.0;
+                if (n3) {
+                    jo_n3 = jo;
+                    if (any_near) lj_block<true, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                    else lj_block<true, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                    e_lj += e_r;
+                } else {
+                    if (any_near) lj_block<false, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                    else lj_block<false, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                    e_lj += 0.5 * e_r;   // each such pair is seen from both lanes
+                }
+            }
+            if constexpr (G > 2) {
+                // reaction forces go back to the lane owning those beads
+                const int dst = gbase + jo_n3;
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    fx[b] += push_f(dst, gx[b]); fy[b] += push_f(dst, gy[b]); fz[b] += push_f(dst, gz[b]);
+                }
+            }
+        }
+
+        // ---- bonded terms over a local window with a two-bead halo ----
+        T lx[L], ly[L], lz[L];
+#pragma unroll
+        for (int b = 0; b < B; ++b) { lx[HALO + b] = px[b]; ly[HALO + b] = py[b]; lz[HALO + b] = pz[b]; }
+        if constexpr (G > 1) {
+            const int prev = gbase + (g > 0 ? g - 1 : 0);
+            const int next = gbase + (g + 1 < G ? g + 1 : G - 1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                lx[h] = pull_f(prev, px[B - 2 + h]); ly[h] = pull_f(prev, py[B - 2 + h]); lz[h] = pull_f(prev, pz[B - 2 + h]);
+                lx[HALO + B + h] = pull_f(next, px[h]); ly[HALO + B + h] = pull_f(next, py[h]); lz[HALO + B + h] = pull_f(next, pz[h]);
+            }
+        }
+        const int ib = i0 - HALO;   // bead index of local slot 0
+        // bond vectors t -> t+1 for t = 0 .. L-2
+        T bx[L - 1], by[L - 1], bz[L - 1], bl[L - 1], bil[L - 1];
+#pragma unroll
+        for (int t = 0; t < L - 1; ++t) {
+            bx[t] = lx[t + 1] - lx[t]; by[t] = ly[t + 1] - ly[t]; bz[t] = lz[t + 1] - lz[t];
+            bl[t] = sqrt_t(bx[t] * bx[t] + by[t] * by[t] + bz[t] * bz[t]);
+            bil[t] = rcp_t(bl[t]);
+        }
+        const T kb = (T)P.k_bond, r0 = (T)P.r0, kth = (T)P.k_angle;
+        // accumulate into local-window forces, then keep the owned part
+        T wx[L], wy[L], wz[L];
+#pragma unroll
+        for (int t = 0; t < L; ++t) { wx[t] = 0; wy[t] = 0; wz[t] = 0; }
+#pragma unroll
+        for (int t = 0; t < L - 1; ++t) {
+            // bond (t, t+1) touches an owned bead?
+            if (t + 1 < HALO || t >= HALO + B) continue;
+            const int i = ib + t;
+            const bool valid = i >= 0 && i + 1 < N;
+            T gsc = kb * (bl[t] - r0) * bil[t];
+            gsc = valid ? gsc : (T)0;
+            wx[t] += gsc * bx[t]; wy[t] += gsc * by[t]; wz[t] += gsc * bz[t];
+            wx[t + 1] -= gsc * bx[t]; wy[t + 1] -= gsc * by[t]; wz[t + 1] -= gsc * bz[t];
+            if (ENERGY && valid && t >= HALO) e_bond += 0.5 * (double)(kb * (bl[t] - r0) * (bl[t] - r0));
+        }
+#pragma unroll
+        for (int t = 0; t < L - 2; ++t) {
+            // angle between bonds t and t+1 (beads t, t+1, t+2) touches an owned bead?
+            if (t + 2 < HALO || t >= HALO + B) continue;
+            const int i = ib + t;
+            const bool valid = i >= 0 && i + 2 < N;
+            const T iab = bil[t] * bil[t + 1];
+            const T c = (bx[t] * bx[t + 1] + by[t] * by[t + 1] + bz[t] * bz[t + 1]) * iab;
+            const T ca = c * bil[t] * bil[t], cb = c * bil[t + 1] * bil[t + 1];
+            const T k = valid ? kth : (T)0;
+            // dU/da = -k (b/(|a||b|) - c a/|a|^2), dU/db = -k (a/(|a||b|) - c b/|b|^2)
+            const T dax = -k * (bx[t + 1] * iab - ca * bx[t]), day = -k * (by[t + 1] * iab - ca * by[t]), daz = -k * (bz[t + 1] * iab - ca * bz[t]);
+            const T dbx = -k * (bx[t] * iab - cb * bx[t + 1]), dby = -k * (by[t] * iab - cb * by[t + 1]), dbz = -k * (bz[t] * iab - cb * bz[t + 1]);
+            wx[t] += dax; wy[t] += day; wz[t] += daz;
+            wx[t + 1] += dbx - dax; wy[t + 1] += dby - day; wz[t + 1] += dbz - daz;
+            wx[t + 2] -= dbx; wy[t + 2] -= dby; wz[t + 2] -= dbz;
+            if (ENERGY && valid && t >= HALO) e_ang += (double)(kth * ((T)1 - c));
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) { fx[b] += wx[HALO + b]; fy[b] += wy[HALO + b]; fz[b] += wz[HALO + b]; }
+
+        // ---- restraint k/2 (xi - centre)^2 on the pulled end ----
+        const int last = N - 1;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (i0 + b == last) {
+                const T dx = px[b] - (T)P.fix_x, dy = py[b] - (T)P.fix_y, dz = pz[b] - (T)P.fix_z;
+                T xi, ux, uy, uz;
+                if (P.rc_mode == 1) { xi = dz; ux = 0; uy = 0; uz = 1; }
+                else { xi = sqrt_t(dx * dx + dy * dy + dz * dz); const T ixi = rcp_t(xi); ux = dx * ixi; uy = dy * ixi; uz = dz * ixi; }
+                const T fr = -(T)P.k * (xi - centre);
+                fx[b] += fr * ux; fy[b] += fr * uy; fz[b] += fr * uz;
+                if (ENERGY) e_res += 0.5 * P.k * (double)(xi - centre) * (double)(xi - centre);
+            }
+        }
+        if (ENERGY) { e[0] = e_bond; e[1] = e_ang; e[2] = e_lj; e[3] = e_res; }
+    }
+};
+
+template <typename T, int G, int B>
+__device__ __forceinline__ void chain_noise(const DevProblem &P, uint32_t gid, uint32_t step, int bead, T z[4]) {
+    Normal4<T>::get(P.seed, gid, step, (uint32_t)bead, 0u, z);
+}
+
+template <typename T, int G, int B>
+__device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkItem &item, char *ws, int64_t step_begin,
+                                               int64_t step_end, double *traj, int64_t traj_rep, double *s_acc) {
+    constexpr int NPAD = G * B;
+    const int tid = threadIdx.x;
+    const int grp = tid / G;
+    const int g = tid % G;
+    const int gbase = lane_id() - g;
+    const int rep = item.rep_begin + grp;
+    const bool active = grp < item.n_reps;
+    const int N = P.n_beads;
+    const int w = item.window;
+    const int64_t gi = (int64_t)w * P.n_replicas + (active ? rep : item.rep_begin);
+    const uint32_t gid = (uint32_t)gi;
+    const double *lam = reinterpret_cast<const double *>(ws + P.off_lambda);
+    const double *x0 = reinterpret_cast<const double *>(ws + P.off_init);
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
+    double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + gi * A_NFIELDS;
+    T *st = state_ptr<T>(ws, P) + gi * 6 * NPAD;
+    const double lam_w = lam[w];
+    const int64_t n_end = step_end < P.n_steps ? step_end : P.n_steps;
+    const int i0 = g * B;
+    const int last = N - 1;
+    const int owner = last / B;       // lane (within group) owning the pulled end
+    double *acc = s_acc + grp * A_NFIELDS;
+
+    T px[B], py[B], pz[B], vx[B], vy[B], vz[B], fx[B], fy[B], fz[B];
+    if (step_begin == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i < N) { px[b] = (T)x0[3 * i]; py[b] = (T)x0[3 * i + 1]; pz[b] = (T)x0[3 * i + 2]; }
+            else { px[b] = 0; py[b] = 0; pz[b] = (T)(P.pad_z0 + P.pad_dz * (i - N)); }
+            vx[b] = 0; vy[b] = 0; vz[b] = 0;
+            if (i > 0 && i < N) {
+                T z[4];
+                chain_noise<T, G, B>(P, gid, 0u, i, z);
+                vx[b] = (T)P.sd_v * z[0]; vy[b] = (T)P.sd_v * z[1]; vz[b] = (T)P.sd_v * z[2];
+            }
+        }
+        if (g == owner) acc_empty(acc);
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            px[b] = st[0 * NPAD + i0 + b]; py[b] = st[1 * NPAD + i0 + b]; pz[b] = st[2 * NPAD + i0 + b];
+            vx[b] = st[3 * NPAD + i0 + b]; vy[b] = st[4 * NPAD + i0 + b]; vz[b] = st[5 * NPAD + i0 + b];
+        }
+        if (g == owner) for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
+    }
+    const bool record = traj != nullptr && gi == traj_rep && active;
+    if (record && step_begin == 0) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (i0 + b < N) { traj[3 * (i0 + b)] = (double)px[b]; traj[3 * (i0 + b) + 1] = (double)py[b]; traj[3 * (i0 + b) + 2] = (double)pz[b]; }
+    }
+    // group-uniform liveness (owner's accumulator holds the flag)
+    const int blown0 = (g == owner) ? (int)acc[A_BLOWN] : 0;
+    const uint64_t bal0 = __ballot(blown0 != 0);
+    bool alive = active && ((bal0 >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) == 0ull;
+
+    ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre_at(P, lam_w, step_begin), px, py, pz, fx, fy, fz, nullptr);
+
+    const T h = (T)(0.5 * P.dt);
+    const T hm = (T)(0.5 * P.dt * P.inv_mass);
+    const T c1 = (T)P.c1, c2sd = (T)P.c2sd;
+    for (int64_t n = step_begin + 1; n <= n_end; ++n) {
+        if (!alive) break;
+        // B, A, O, A on the mobile beads (bead 0 and padding stay put)
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i > 0 && i < N) {
+                T z[4];
+                chain_noise<T, G, B>(P, gid, (uint32_t)n, i, z);
+                vx[b] += hm * fx[b]; vy[b] += hm * fy[b]; vz[b] += hm * fz[b];
+                px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
+                vx[b] = c1 * vx[b] + c2sd * z[0]; vy[b] = c1 * vy[b] + c2sd * z[1]; vz[b] = c1 * vz[b] + c2sd * z[2];
+                px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
+            }
+        }
+        ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre_at(P, lam_w, n), px, py, pz, fx, fy, fz, nullptr);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i > 0 && i < N) { vx[b] += hm * fx[b]; vy[b] += hm * fy[b]; vz[b] += hm * fz[b]; }
+        }
+        if (record && n <= 100000) {
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (i0 + b < N) {
+                    double *o = traj + (int64_t)n * 3 * N + 3 * (i0 + b);
+                    o[0] = (double)px[b]; o[1] = (double)py[b]; o[2] = (double)pz[b];
+                }
+        }
+        if (sample_now(P, n)) {
+            bool ok = true;
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+                if (i0 + b < N) ok = ok && isfinite((double)px[b]) && isfinite((double)py[b]) && isfinite((double)pz[b]);
+            double xi = 0.0;
+            if (g == owner) {
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+                    if (i0 + b == last) {
+                        const double dx = (double)px[b] - P.fix_x, dy = (double)py[b] - P.fix_y, dz = (double)pz[b] - P.fix_z;
+                        xi = P.rc_mode == 1 ? dz : sqrt(dx * dx + dy * dy + dz * dz);
+                    }
+                ok = ok && isfinite(xi) && fabs(xi) <= P.xi_bound;
+            }
+            const uint64_t bad = __ballot(!ok);
+            const bool grp_bad = ((bad >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) != 0ull;
+            if (grp_bad) {
+                if (g == owner) acc[A_BLOWN] = 1.0;
+                alive = false;
+            } else if (g == owner) {
+                accumulate(P, lam, w, xi, acc, hist);
+            }
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            st[0 * NPAD + i0 + b] = px[b]; st[1 * NPAD + i0 + b] = py[b]; st[2 * NPAD + i0 + b] = pz[b];
+            st[3 * NPAD + i0 + b] = vx[b]; st[4 * NPAD + i0 + b] = vy[b]; st[5 * NPAD + i0 + b] = vz[b];
+        }
+        if (g == owner) for (int f = 0; f < A_NFIELDS; ++f) acc_g[f] = acc[f];
+    }
+}
+
+// Direct launch: one work item per workgroup.
+template <typename T, int G, int B>
+__global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
+                                                int n_items, char *__restrict__ ws, int64_t step_begin,
+                                                int64_t step_end, double *__restrict__ traj, int64_t traj_rep) {
+    __shared__ double s_acc[(WG / G) * A_NFIELDS];
+    if ((int)blockIdx.x >= n_items) return;
+    const WorkItem item = items[blockIdx.x];
+    run_chain_item<T, G, B>(probs[item.prob], item, ws, step_begin, step_end, traj, traj_rep, s_acc);
+}
+
+// Persistent launch: workgroups take items from a queue (atomic ticket) until
+// it is empty; items are ordered longest first by the host.
+template <typename T, int G, int B>
+__global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__restrict__ probs,
+                                                           const WorkItem *__restrict__ items, int n_items,
+                                                           int *__restrict__ ticket, char *__restrict__ ws) {
+    __shared__ double s_acc[(WG / G) * A_NFIELDS];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const WorkItem item = items[it];
+        run_chain_item<T, G, B>(probs[item.prob], item, ws, 0, INT64_MAX, nullptr, -1, s_acc);
+    }
+}
+
+// Energies and forces of configurations (parity hook): one group per configuration.
+template <typename T, int G, int B>
+__global__ __launch_bounds__(WG) void chain_eval(const DevProblem *__restrict__ probs, const double *__restrict__ coords,
+                                                 int n_rep, double centre, double *__restrict__ forces,
+                                                 double *__restrict__ energy) {
+    const DevProblem &P = probs[0];
+    const int tid = threadIdx.x;
+    const int grp = tid / G, g = tid % G;
+    const int gbase = lane_id() - g;
+    const int c = blockIdx.x * (WG / G) + grp;
+    const bool active = c < n_rep;
+    const int cc = active ? c : 0;
+    const int N = P.n_beads;
+    const int i0 = g * B;
+    T px[B], py[B], pz[B], fx[B], fy[B], fz[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = i0 + b;
+        if (i < N) { px[b] = (T)coords[(int64_t)cc * 3 * N + 3 * i]; py[b] = (T)coords[(int64_t)cc * 3 * N + 3 * i + 1]; pz[b] = (T)coords[(int64_t)cc * 3 * N + 3 * i + 2]; }
+        else { px[b] = 0; py[b] = 0; pz[b] = (T)(P.pad_z0 + P.pad_dz * (i - N)); }
+    }
+    double e[4];
+    ChainForce<T, G, B, true>::compute(P, g, gbase, (T)centre, px, py, pz, fx, fy, fz, e);
+    // group sums of the energy parts (fixed order over lanes)
+    double tot[4];
+    for (int q = 0; q < 4; ++q) {
+        double s = 0.0;
+        for (int l = 0; l < G; ++l) s += pull_f(gbase + l, e[q]);
+        tot[q] = s;
+    }
+    if (!active) return;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int i = i0 + b;
+        if (i < N) {
+            forces[(int64_t)c * 3 * N + 3 * i] = (double)fx[b];
+            forces[(int64_t)c * 3 * N + 3 * i + 1] = (double)fy[b];
+            forces[(int64_t)c * 3 * N + 3 * i + 2] = (double)fz[b];
+        }
+    }
+    if (g == 0) {
+        energy[c * 5 + 0] = tot[0] + tot[1] + tot[2] + tot[3];
+        for (int q = 0; q < 4; ++q) energy[c * 5 + 1 + q] = tot[q];
+    }
+}
+
+template <typename T>
+__global__ void pot1d_eval(const DevProblem *__restrict__ probs, const double *__restrict__ coords, int n_rep,
+                           double centre, double *__restrict__ forces, double *__restrict__ energy) {
+    const DevProblem &P = probs[0];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_rep) return;
+    const T x = (T)coords[c];
+    forces[c] = (double)force_1d<T>(P, x, (T)centre);
+    double ho;
+    if (P.pot_kind == 0) { const double q = (double)x * (double)x - P.pot_b; ho = P.pot_a * q * q; }
+    else ho = 0.5 * P.pot_kappa * (double)x * (double)x;
+    const double res = 0.5 * P.k * ((double)x - centre) * ((double)x - centre);
+    energy[c * 5 + 0] = ho + res; energy[c * 5 + 1] = ho; energy[c * 5 + 2] = 0; energy[c * 5 + 3] = 0; energy[c * 5 + 4] = res;
+}
+
+// Per-shape launchers; each shape is instantiated in its own translation unit.
+template <typename T, int G, int B>
+hipError_t launch_chain_direct(const DevProblem *d_probs, const WorkItem *d_items, int n_items, char *ws,
+                               int64_t step_begin, int64_t step_end, double *traj, int64_t traj_rep, hipStream_t stream) {
+    hipLaunchKernelGGL((sim_chain<T, G, B>), dim3(n_items), dim3(WG), 0, stream, d_probs, d_items, n_items, ws,
+                       step_begin, step_end, traj, traj_rep);
+    return hipGetLastError();
+}
+template <typename T, int G, int B>
+hipError_t launch_chain_persistent(const DevProblem *d_probs, const WorkItem *d_items, int n_items, int *d_ticket,
+                                   char *ws, int n_groups, hipStream_t stream) {
+    hipLaunchKernelGGL((sim_chain_persistent<T, G, B>), dim3(n_groups), dim3(WG), 0, stream, d_probs, d_items,
+                       n_items, d_ticket, ws);
+    return hipGetLastError();
+}
+template <typename T, int G, int B>
+hipError_t launch_chain_eval(const DevProblem *d_probs, const double *coords, int n_rep, double centre,
+                             double *forces, double *energy, hipStream_t stream) {
+    const int per = WG / G;
+    const int nb = (n_rep + per - 1) / per;
+    hipLaunchKernelGGL((chain_eval<T, G, B>), dim3(nb), dim3(WG), 0, stream, d_probs, coords, n_rep, centre, forces,
+                       energy);
+    return hipGetLastError();
+}
+template <typename T, int G, int B>
+int chain_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sim_chain_persistent<T, G, B>, WG, 0) != hipSuccess) n = 1;
+    return n;
+}
+
+#define PPP_INSTANTIATE_SHAPE(T, G, B)                                                                              \
+    template hipError_t launch_chain_direct<T, G, B>(const DevProblem *, const WorkItem *, int, char *, int64_t,   \
+                                                     int64_t, double *, int64_t, hipStream_t);                     \
+    template hipError_t launch_chain_persistent<T, G, B>(const DevProblem *, const WorkItem *, int, int *, char *, \
+                                                         int, hipStream_t);                                        \
+    template hipError_t launch_chain_eval<T, G, B>(const DevProblem *, const double *, int, double, double *,      \
+                                                   double *, hipStream_t);                                         \
+    template int chain_blocks_per_cu<T, G, B>();
+
+}  // namespace ppp

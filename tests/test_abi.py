@@ -1,0 +1,114 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol the
+header declares, and validates problems before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1105_4840_amd as ppp
+import ppp_inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ppp.h")).read()
+    return sorted(set(re.findall(r"^(?:ppp_status|const char \*)\s*(ppp_\w+)\(", text, flags=re.M)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", ppp.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (ppp_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = ppp.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+    assert set(ppp.EXPORTED) >= set(names)
+
+
+def _status(prob):
+    p, keep = ppp.make_problem(prob)
+    h = ctypes.c_void_p()
+    st = ppp.lib().ppp_create(ctypes.byref(p), ctypes.byref(h))
+    if st == 0:
+        ppp.lib().ppp_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: p.update(k=0.0),
+    lambda p: p.update(kT=-1.0),
+    lambda p: p.update(dt=float("nan")),
+    lambda p: p.update(n_replicas=0),
+    lambda p: p.update(sample_every=0),
+    lambda p: p.update(n_equil=p["n_steps"]),
+    lambda p: p.update(xi_nbins=0),
+    lambda p: p.update(xi_bin=0.0),
+    lambda p: p.update(w_bin=0.0),
+    lambda p: p.update(n_blocks=10 ** 6),
+    lambda p: p.update(n_blocks=-1),
+    lambda p: p.update(flags=1),
+    lambda p: p.update({"lambda": [0.0]}),
+    lambda p: p.update({"lambda": [0.0, 1.0, 1.0]}),
+    lambda p: p.update({"lambda": [0.0, 1.0, 0.5]}),
+    lambda p: p.update({"lambda": [0.0, float("inf")]}),
+    lambda p: p.update(n_beads=1),
+    lambda p: p.update(n_beads=100000),
+    lambda p: p.update(mass=0.0),
+    lambda p: p.update(rc_mode=3),
+])
+def test_invalid_chain_problems_rejected(mutate):
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    mutate(p)
+    assert _status(p) == ppp.PPP_E_INVALID_ARG
+
+
+def test_invalid_1d_problems_rejected():
+    p = ppp_inputs.config_1d(n_replicas=4, n_steps=100)
+    p["mobility"] = 0.0
+    assert _status(p) == ppp.PPP_E_INVALID_ARG
+    p = ppp_inputs.config_1d(n_replicas=4, n_steps=100)
+    p["integrator_1d"] = 7
+    assert _status(p) == ppp.PPP_E_INVALID_ARG
+    p = ppp_inputs.config_1d(n_replicas=4, n_steps=100)
+    p["pot_kind"] = 9
+    assert _status(p) == ppp.PPP_E_INVALID_ARG
+
+
+def test_valid_problems_and_workspace_size():
+    for p in (ppp_inputs.config_1d(), ppp_inputs.config_chain10(), ppp_inputs.config_chain32(),
+              ppp_inputs.config_chain256()):
+        h = ppp.ppp_create(p)
+        n = ppp.ppp_workspace_size(h)
+        assert n > 0 and n % 256 == 0
+        ppp.ppp_destroy(h)
+    # descending windows are allowed too
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    p["lambda"] = p["lambda"][::-1]
+    assert _status(p) == 0
+
+
+def test_error_strings():
+    L = ppp.lib()
+    for s in range(7):
+        assert L.ppp_status_string(s)
+    assert L.ppp_last_error(None) == b""
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    p["k"] = -1.0
+    with pytest.raises(ppp.PppError) as e:
+        ppp.ppp_create(p)
+    assert "k must be" in str(e.value)
+
+
+def test_batch_rejects_1d():
+    with pytest.raises(ppp.PppError):
+        ppp.ppp_batch_create([ppp_inputs.config_1d(n_replicas=4, n_steps=100)])
+    h = ppp.ppp_batch_create(ppp_inputs.batched_instances(6, seed=3))
+    assert ppp.ppp_workspace_size(h) > 0
+    ppp.ppp_destroy(h)

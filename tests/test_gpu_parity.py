@@ -1,0 +1,238 @@
+"""GPU path against the CPU oracle, through the C ABI (needs an MI355X).
+
+Deterministic parity: Philox words bit-exact; single-step forces and energies
+(fp64 mode 1e-12, fp32 mode 1e-5, relative, norm-wise per configuration);
+<= 100-step fp64 trajectories within 1e-10; whole fp64 runs: sample counts and
+histograms exact, moments, log-sum-exp and profiles to 1e-9.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1105_4840_amd as ppp
+import ppp_inputs
+from oracle import estimators
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_philox_bits_and_normals():
+    _say("case philox")
+    n = 4096
+    for seed, c1, c2, c3 in [(0, 0, 0, 0), (123456789012345, 7, 11, 0), (2 ** 64 - 1, 2 ** 32 - 1, 5, 9)]:
+        w, z64, z32 = ppp.ppp_philox(seed, 1000, c1, c2, c3, n)
+        for i in range(0, n, 97):
+            ref = oracle.philox([seed & 0xFFFFFFFF, seed >> 32], [1000 + i, c1, c2, c3])
+            assert [int(x) for x in w[i]] == ref
+            zr = oracle.normals4(seed, 1000 + i, c1, c2, c3)
+            assert np.max(np.abs(z64[i] - zr)) < 1e-13
+            # fp32 deviates: 23-bit uniforms and hardware transcendentals
+            assert np.max(np.abs(z32[i] - zr)) < 2e-4 * (1 + np.max(np.abs(zr)))
+    from scipy import stats
+    assert abs(z32.mean()) < 0.02 and abs(z32.var() - 1) < 0.03
+    assert stats.kstest(z32.ravel(), "norm").pvalue > 1e-4
+
+
+FORCE_CASES = [2, 3, 4, 9, 10, 13, 16, 23, 32, 37, 64, 100, 128, 200, 256, 300]
+
+
+@pytest.mark.parametrize("n_beads", FORCE_CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_chain_forces(n_beads, precision):
+    _say(f"case forces N={n_beads} {precision}")
+    prob = ppp_inputs.config_chain_small(n_beads, n_replicas=4, n_steps=10, precision=precision)
+    conf = ppp_inputs.random_chain_coords(n_beads, 5, seed=n_beads)
+    lam = 0.6 * (n_beads - 1)
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        x = torch.tensor(conf.reshape(len(conf), -1), dtype=torch.float64, device="cuda")
+        f, e = ppp.ppp_eval_forces(h, ws, x, lam)
+        f = f.cpu().numpy().reshape(len(conf), -1, 3); e = e.cpu().numpy()
+    finally:
+        ppp.ppp_destroy(h)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for c in range(len(conf)):
+        etot, parts, fr = oracle.chain_forces(prob, conf[c], lam)
+        assert np.linalg.norm(f[c] - fr) <= tol * np.linalg.norm(fr), (c, np.linalg.norm(f[c] - fr), np.linalg.norm(fr))
+        scale = np.sum(np.abs(parts)) + 1.0
+        assert abs(e[c, 0] - etot) <= tol * scale
+        assert np.all(np.abs(e[c, 1:] - parts) <= tol * scale)
+
+
+def test_pot1d_forces():
+    _say("case forces 1d")
+    for precision, tol in (("fp64", 1e-13), ("fp32", 1e-5)):
+        prob = ppp_inputs.config_1d(n_replicas=4, n_steps=10, precision=precision)
+        xs = np.linspace(-2, 2, 33)
+        h = ppp.ppp_create(prob)
+        try:
+            ws = ppp.workspace(h)
+            f, e = ppp.ppp_eval_forces(h, ws, torch.tensor(xs[:, None], device="cuda", dtype=torch.float64), 0.3)
+            f = f.cpu().numpy()[:, 0]; e = e.cpu().numpy()
+        finally:
+            ppp.ppp_destroy(h)
+        for i, x in enumerate(xs):
+            er, Fr = oracle.pot1d(prob, x, 0.3)
+            assert abs(f[i] - Fr) <= tol * (1 + abs(Fr))
+            assert abs(e[i, 0] - er) <= tol * (1 + abs(er))
+
+
+@pytest.mark.parametrize("n_beads,window,replica", [(10, 1, 5), (13, 0, 3), (32, 2, 7), (37, 1, 2), (64, 3, 1),
+                                                    (100, 1, 0), (256, 2, 1)])
+def test_chain_trajectory_fp64(n_beads, window, replica):
+    _say(f"case trajectory N={n_beads}")
+    prob = ppp_inputs.config_chain_small(n_beads, n_replicas=8, n_steps=100, n_windows=4, precision="fp64")
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        tr = ppp.ppp_trajectory(h, ws, window, replica, 100, 3 * n_beads).cpu().numpy()
+    finally:
+        ppp.ppp_destroy(h)
+    ref = oracle.trajectory(prob, window, replica, 100)
+    assert np.max(np.abs(tr - ref)) < 1e-10, np.max(np.abs(tr - ref))
+
+
+def test_1d_trajectory_fp64():
+    _say("case trajectory 1d")
+    prob = ppp_inputs.config_1d(n_replicas=300, n_steps=100, precision="fp64")
+    for integ in (0, 1):
+        prob["integrator_1d"] = integ
+        h = ppp.ppp_create(prob)
+        try:
+            ws = ppp.workspace(h)
+            tr = ppp.ppp_trajectory(h, ws, 3, 260, 100, 1).cpu().numpy()
+        finally:
+            ppp.ppp_destroy(h)
+        ref = oracle.trajectory(prob, 3, 260, 100)
+        assert np.max(np.abs(tr - ref)) < 1e-10
+
+
+def _compare_runs(prob, res, ref, prof_tol=1e-9):
+    assert np.array_equal(res["n_samples"], ref["n_samples"])
+    assert np.array_equal(res["n_blown_up"], ref["n_blown_up"])
+    assert np.array_equal(res["xi_hist"].astype(np.int64), ref["xi_hist"])
+    assert np.array_equal(res["xi_under_over"].astype(np.int64), ref["xi_under_over"])
+    for key in ("xi_mean", "xi_std", "gamma2", "xi_min_sample", "xi_max_sample"):
+        assert np.allclose(res[key], ref[key], rtol=1e-10, atol=1e-12, equal_nan=True), key
+    s = len(prob["lambda"])
+    assert np.allclose(res["lse_fwd"][:s - 1], ref["lse_fwd"][:s - 1], rtol=1e-11, atol=1e-9)
+    assert np.allclose(res["lse_rev"][1:], ref["lse_rev"][1:], rtol=1e-11, atol=1e-9)
+    for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com", "dF_unc", "dF_rev"):
+        assert np.max(np.abs(res[key] - ref[key])) < prof_tol * (1 + np.max(np.abs(ref[key]))), key
+    for key in ("dF_je_se", "dF_fluct_se", "dF_gauss_se", "dF_com_se"):
+        assert np.allclose(res[key][1:], ref[key][1:], rtol=1e-7, atol=1e-12), key
+    for key in ("kish_frac", "overlap_ovl", "dlambda_over_sigma", "dlambda_over_reach"):
+        assert np.allclose(res[key], ref[key][:s - 1], rtol=1e-9, atol=1e-12), key
+    assert np.array_equal(res["criterion_ok"].astype(bool), ref["criterion_ok"][:s - 1])
+    if int(prob.get("w_half_bins", 0)) > 0:
+        assert np.max(np.abs(res["work_hist"] - ref["work_hist"])) < 1e-12
+        for key in ("dF_je_hist", "dF_je_hist_mid"):
+            assert np.max(np.abs(res[key] - ref[key])) < 1e-8, key
+        assert np.array_equal(res["q_bins"], ref["q_bins"])
+        assert np.allclose(res["sigma_w"], ref["sigma_w"], rtol=1e-9, atol=1e-12)
+        assert np.allclose(res["dF_je_var_paper"], ref["dF_je_var_paper"], rtol=1e-8, atol=1e-14)
+        assert np.allclose(res["work_lost"], ref["work_lost"], atol=1e-12)
+
+
+RUN_CASES = [
+    ("1d", dict(n_replicas=300, n_steps=3000, n_windows=21), None),
+    ("1d-em", dict(n_replicas=70, n_steps=2000, n_windows=6), {"integrator_1d": 1}),
+    ("1d-pull", dict(n_replicas=40, n_steps=2000, n_windows=6), {"n_pull": 500}),
+    ("chain10", 10, dict(n_replicas=70, n_steps=600, n_windows=5)),
+    ("chain32", 32, dict(n_replicas=70, n_steps=400, n_windows=4)),
+    ("chain37", 37, dict(n_replicas=20, n_steps=300, n_windows=4)),
+    ("chain100", 100, dict(n_replicas=20, n_steps=300, n_windows=3)),
+    ("chain256-pull", 256, dict(n_replicas=5, n_steps=200, n_windows=3)),
+]
+
+
+@pytest.mark.parametrize("case", RUN_CASES, ids=[c[0] for c in RUN_CASES])
+def test_run_parity_fp64(case):
+    name = case[0]
+    _say(f"case run {name}")
+    if name.startswith("1d"):
+        prob = ppp_inputs.config_1d(precision="fp64", **case[1])
+        if case[2]:
+            prob.update(case[2])
+        prob["w_half_bins"] = 3000
+    else:
+        prob = ppp_inputs.config_chain_small(case[1], precision="fp64", **case[2])
+        prob["w_half_bins"] = 3000
+        if name.endswith("pull"):
+            prob["n_pull"] = 100
+            prob["n_equil"] = 100
+    res, tim = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+
+
+def test_checkpoint_resume_is_bit_identical():
+    _say("case checkpoint")
+    prob = ppp_inputs.config_chain_small(13, n_replicas=40, n_steps=800, n_windows=4, precision="fp64")
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        ppp.ppp_run(h, ws)
+        full = ppp.ppp_get_result(h, prob)
+        ppp.ppp_begin(h, ws)
+        ppp.ppp_advance(h, 333)
+        blob = ppp.ppp_checkpoint(h)
+        assert ppp.ppp_steps_done(h) == 333
+    finally:
+        ppp.ppp_destroy(h)
+    h2 = ppp.ppp_create(prob)
+    try:
+        ws2 = ppp.workspace(h2)
+        ppp.ppp_restore(h2, ws2, blob)
+        ppp.ppp_advance(h2, 10 ** 9)
+        ppp.ppp_finalize(h2)
+        part = ppp.ppp_get_result(h2, prob)
+    finally:
+        ppp.ppp_destroy(h2)
+    for key in ("dF_je", "dF_fluct", "xi_mean", "xi_hist", "n_samples"):
+        assert np.array_equal(full[key], part[key]), key
+
+
+def test_frozen_replicas_are_counted():
+    _say("case blowup")
+    prob = ppp_inputs.config_chain_small(10, n_replicas=16, n_steps=100, n_windows=3, precision="fp32")
+    init = ppp_inputs.random_chain_coords(10, 1, seed=4)[0]
+    init[5, 1] = np.nan
+    prob["init_coords"] = init.ravel().tolist()
+    res, _ = ppp.run(prob)
+    assert res["status"] == ppp.PPP_E_NUMERICAL
+    assert np.all(res["n_blown_up"] == 16) and np.all(res["n_samples"] == 0)
+
+
+def test_fp32_chain_statistics_match_oracle():
+    """fp32 forces with fp64 accumulation: final dF within 3 combined standard errors of the fp64 oracle."""
+    _say("case fp32 statistics chain10")
+    prob = ppp_inputs.config_chain10(n_replicas=128, n_steps=6000)
+    prob["n_blocks"] = 16
+    res, _ = ppp.run(prob)
+    p64 = dict(prob, precision="fp64")
+    xi, kept, _ = oracle.run(p64)
+    ref = estimators.estimate(p64, xi, kept, with_appc=False)
+    for key in ("dF_je", "dF_fluct", "dF_gauss"):
+        se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
+        assert abs(res[key][-1] - ref[key][-1]) < 3.5 * se, (key, res[key][-1], ref[key][-1], se)
