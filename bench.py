@@ -1,0 +1,161 @@
+"""Throughput benchmark of the parallel pulling protocol on one MI355X.
+
+One step = one whole pass of the protocol on one batch of synthetic input:
+initial state, all relaxation steps of every replica of every window,
+reductions, estimators (Eqs. 12-14, jackknife, overlap) and App. C work
+distributions, with inputs resident in device memory.  `value` is the number
+of replica-steps (one integrator step of one replica, with its force
+evaluation, noise, sampling and accumulation) per second of wall time.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("replica-steps/sec and ΔF abs error (kT) at equal budget: plain vs batched+learned windows")
+FP32_PEAK = 157.3e12     # MI355X fp32 vector, TFLOP/s (packed); unpacked FMA peak is half
+FP64_PEAK = 78.6e12
+
+
+def chain_flops_per_replica_step(n_beads):
+    """Algorithmic fp32 flops of one replica-step of the chain: 24 per non-excluded
+    Lennard-Jones pair (all |i-j| > 2 pairs are evaluated), 21 per bond, 45 per
+    angle, 11 per mobile degree of freedom (BAOAB) and 15 for the restraint."""
+    n = n_beads
+    pairs = max(0, n * (n - 1) // 2 - (n - 1) - max(0, n - 2))
+    return 24 * pairs + 21 * (n - 1) + 45 * max(0, n - 2) + 11 * 3 * (n - 1) + 15
+
+
+WORKLOADS = {
+    "chain10": ("config_chain10", "10-bead chain (bonds k_b=100, cosine angles k_theta=5, LJ eps=sigma=1 rc=2.5), "
+                "end-to-end restraint k=20, 21 windows in [1.5, 8.5], 1024 replicas/window, 40000 BAOAB steps "
+                "dt=0.005 kT=1, fp32 forces/integration, fp64 work/LSE/estimators"),
+    "chain32": ("config_chain32", "32-bead chain, same force field, k=20, 21 uniform windows in [3, 28], "
+                "4096 replicas/window, 23251 steps (2e9 replica-steps)"),
+    "chain256": ("config_chain256", "256-bead chain, same force field, all LJ pairs, k=20, 41 windows in [10, 200], "
+                 "4096 replicas/window, 200000 steps"),
+    "1d": ("config_1d", "1-D double well U=5(x^2-1)^2, k=50, 21 windows in [-1.5, 1.5], 256 replicas/window, "
+           "20000 overdamped LM steps dt=1e-3, fp64"),
+}
+
+
+def cpu_baseline(prob, target_seconds):
+    """The fp64 oracle on a bounded sample of the same workload: every window, the full
+    per-replica step count, fewer replicas."""
+    import numpy as np
+    import oracle
+    p = dict(prob)
+    steps_total = len(p["lambda"]) * p["n_steps"]
+    # calibrate on a tiny sample, then size the measured one
+    p["n_replicas"] = 2
+    t0 = time.time(); _, _, threads = oracle.run(p); t_cal = max(time.time() - t0, 1e-3)
+    rate = 2 * steps_total / t_cal
+    reps = int(max(2, min(prob["n_replicas"], target_seconds * rate / steps_total)))
+    p["n_replicas"] = reps
+    t0 = time.time(); xi, kept, threads = oracle.run(p); el = time.time() - t0
+    rs = reps * steps_total
+    return {"value": rs / el, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(p['lambda'])} windows x {reps} replicas x {p['n_steps']} steps "
+                      f"({rs:.3g} replica-steps, {el:.1f} s, fp64 C, OpenMP over replicas)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chain10", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0, help="advance in chunks of this many steps (progress lines)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs the protocol on one GPU; --gpus must be 1 "
+              "(the path shards by windows and replica blocks, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1105_4840_amd as ppp
+    import ppp_inputs
+
+    fn, desc = WORKLOADS[args.workload]
+    prob = getattr(ppp_inputs, fn)()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    h = ppp.ppp_create(prob)
+    ws = ppp.workspace(h)
+    rs_per_run = len(prob["lambda"]) * prob["n_replicas"] * prob["n_steps"]
+
+    def one_run():
+        if args.chunk > 0:
+            ppp.ppp_begin(h, ws, stream)
+            done = 0
+            while done < prob["n_steps"]:
+                ppp.ppp_advance(h, args.chunk, stream)
+                torch.cuda.synchronize()
+                done = ppp.ppp_steps_done(h)
+                print(f"# progress {done}/{prob['n_steps']} steps", file=sys.stderr, flush=True)
+            ppp.ppp_finalize(h, stream)
+        else:
+            ppp.ppp_run(h, ws, stream)
+
+    for _ in range(args.warmup):
+        one_run()
+    torch.cuda.synchronize()
+    sim_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_run()
+        t = ppp.ppp_get_timings(h)          # HIP events on the launch stream
+        sim_ms.append(t["sim_ms"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = ppp.ppp_get_result(h, prob)
+    tim = ppp.ppp_get_timings(h)
+    ppp.ppp_destroy(h)
+
+    value = rs_per_run * args.steps / el
+    avg_sim_s = float(np.mean(sim_ms)) * 1e-3
+    if prob["model"] == "chain":
+        flops = chain_flops_per_replica_step(prob["n_beads"]) * rs_per_run
+        roof = {"bound": "alu", "achieved": flops / avg_sim_s / 1e12, "peak": FP32_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": flops / avg_sim_s / FP32_PEAK, "traffic": None,
+                "kernel": f"sim_chain<float,{tim['variant_lanes']},{tim['variant_beads_per_lane']}>",
+                "flops_per_replica_step": chain_flops_per_replica_step(prob["n_beads"]),
+                "avg_launch_ms": avg_sim_s * 1e3}
+    else:
+        flops = 12 * rs_per_run
+        roof = {"bound": "alu", "achieved": flops / avg_sim_s / 1e12, "peak": FP64_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": flops / avg_sim_s / FP64_PEAK, "traffic": None,
+                "kernel": "sim_1d<double>", "flops_per_replica_step": 12, "avg_launch_ms": avg_sim_s * 1e3}
+    out = {
+        "metric": METRIC, "value": value, "unit": "replica-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prob.get("precision") == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "windows": len(prob["lambda"]),
+                   "replicas_per_window": prob["n_replicas"], "relaxation_steps": prob["n_steps"],
+                   "replica_steps_per_step": rs_per_run, "parallelism": "1 GPU"},
+        "kernel_replica_steps_per_s": rs_per_run / avg_sim_s,
+        "phase_ms": {"sim": tim["sim_ms"], "reduce_estimators": tim["reduce_ms"], "appc": tim["appc_ms"]},
+        "accuracy": {"dF_je_end": float(res["dF_je"][-1]), "dF_je_se_end": float(res["dF_je_se"][-1]),
+                     "dF_fluct_end": float(res["dF_fluct"][-1]), "dF_com_unc_end": float(res["dF_unc"][-1]),
+                     "frozen_replicas": int(res["n_blown_up"].sum())},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,8 +155,9 @@ typedef struct {
 
 typedef struct ppp_handle ppp_handle;
 
-/* Validates and copies the problem, chooses the kernel shape and the
- * workspace layout.  PPP_E_INVALID_ARG for: s < 2, lambda not strictly
+/* Validates and copies the problem, chooses the kernel shape (from the table
+ * file named by the environment variable PPP_TUNE_TABLE if set, see
+ * ppp_autotune, else a built-in heuristic) and the workspace layout.  PPP_E_INVALID_ARG for: s < 2, lambda not strictly
  * monotone or non-finite, k, kT, dt <= 0, n_replicas < 1, sample_every < 1,
  * n_equil < 0 or >= n_steps, K < 1, xi_bin <= 0, w_bin <= 0 with M > 0,
  * chain with n_beads < 2 or > PPP_MAX_BEADS, non-positive mass or bond
@@ -215,7 +216,8 @@ const char *ppp_last_error(const ppp_handle *h); /* NULL-safe; "" when no error 
  * problem's precision.  Uses (and clobbers) d_workspace of h (a later ppp_run
  * starts afresh).  d_coords: device fp64 [n_rep][dof]; d_forces: device fp64
  * [n_rep][dof]; d_energy: device fp64 [n_rep][5] = {total, bond, angle, lj,
- * restraint} (1-D: {total, H_o, 0, 0, restraint}); dof = 3 n_beads or 1. */
+ * restraint} (1-D: {total, H_o, 0, 0, restraint}); dof = 3 n_beads or 1.
+ * Bead 0 is held fixed, so its force omits the restraint's reaction. */
 ppp_status ppp_eval_forces(ppp_handle *h, void *d_workspace, size_t bytes, const double *d_coords,
                            int32_t n_rep, double lambda, double *d_forces, double *d_energy,
                            void *hip_stream);

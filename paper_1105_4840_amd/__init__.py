@@ -90,6 +90,9 @@ def lib():
     """Loads libppp.so; raises if it is not built (there is no CPU fallback)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname; loading torch first makes
+        # libppp bind to that one, so the process holds a single HIP runtime
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libppp.so not found at {LIB_PATH}: build it with __graft_entry__.build() "
                               "(python paper_1105_4840_amd/build.py)")

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -155,15 +156,18 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
 
 // Kernel shape (lanes per replica G, beads per lane B) for a chain length.
 void default_shape(int N, int &G, int &B) {
+    // measured on MI355X: short chains want a few lanes per replica to fill the
+    // chip; long chains want more beads per lane for fewer rotation rounds
     if (N <= 4) { G = 1; B = 4; }
     else if (N <= 8) { G = 1; B = 8; }
-    else if (N <= 12) { G = 1; B = 12; }
-    else if (N <= 16) { G = 1; B = 16; }
-    else if (N <= 32) { G = 4; B = 8; }
+    else if (N <= 10) { G = 2; B = 5; }
+    else if (N <= 16) { G = 2; B = 8; }
+    else if (N <= 32) { G = 16; B = 2; }
     else if (N <= 64) { G = 16; B = 4; }
     else if (N <= 128) { G = 16; B = 8; }
     else if (N <= 256) { G = 64; B = 4; }
     else { G = 64; B = 8; }
+}
 }
 
 struct TuneEntry { int nmax, precision, G, B; };
@@ -508,7 +512,8 @@ ppp_status ppp_create(const ppp_problem *p, ppp_handle **out) {
     if (!h) return PPP_E_OUT_OF_MEMORY;
     h->probs.resize(1);
     std::string msg;
-    ppp_status s = build_problem(p, h->probs[0], {}, msg);
+    // an optional shape table (written by ppp_autotune) named by PPP_TUNE_TABLE
+    ppp_status s = build_problem(p, h->probs[0], read_tune_table(std::getenv("PPP_TUNE_TABLE")), msg);
     if (s != PPP_OK) { g_create_err = msg; delete h; return s; }
     make_items(h->probs[0], 0, h->items);
     finish_layout(h);
@@ -523,7 +528,7 @@ ppp_status ppp_batch_create(const ppp_problem *ps, int32_t n, const char *tune_t
     ppp_handle *h = new (std::nothrow) ppp_handle();
     if (!h) return PPP_E_OUT_OF_MEMORY;
     h->batch = true;
-    const std::vector<TuneEntry> tune = read_tune_table(tune_table_path);
+    const std::vector<TuneEntry> tune = read_tune_table(tune_table_path ? tune_table_path : std::getenv("PPP_TUNE_TABLE"));
     h->probs.resize(n);
     for (int i = 0; i < n; ++i) {
         std::string msg;

