@@ -168,7 +168,6 @@ void default_shape(int N, int &G, int &B) {
     else if (N <= 256) { G = 64; B = 4; }
     else { G = 64; B = 8; }
 }
-}
 
 struct TuneEntry { int nmax, precision, G, B; };
 
