@@ -18,9 +18,11 @@ __device__ __forceinline__ U4 philox(uint64_t seed, uint32_t c0, uint32_t c1, ui
     uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-        uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        // one 32x32->64 multiply each (v_mad_u64_u32) instead of separate hi/lo products
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         uint32_t n0 = hi1 ^ c1 ^ k0;
         uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;

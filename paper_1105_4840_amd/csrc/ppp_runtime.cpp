@@ -55,7 +55,7 @@ struct ppp_handle {
     // run state
     char *ws = nullptr;
     hipStream_t stream = nullptr;
-    bool begun = false, finalized = false, ran = false;
+    bool begun = false, finalized = false, ran = false, restored = false;
     int64_t steps_done = 0;
     std::string err;
     hipEvent_t ev[6] = {};
@@ -439,11 +439,9 @@ ppp_status do_begin(ppp_handle *h, void *ws, size_t bytes, hipStream_t st) {
     HIPCHK(h, hipEventRecord(h->ev[0], st));
     HIPCHK(h, launch_init(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_k, h->max_m,
                           reinterpret_cast<int *>(h->ws + h->off_tickets), 64, st));
-    // step range [0, 0]: initial state and empty accumulators
-    for (auto &ph : h->probs)
-        if ((s = launch_items(h, ph, 0, 0, st, nullptr, -1, ph.first_item, ph.n_items)) != PPP_OK) return s;
+    // the first advance starts at step 0, where the kernel builds the initial state
     HIPCHK(h, hipEventRecord(h->ev[1], st));
-    h->begun = true; h->finalized = false; h->steps_done = 0; h->sim_launches = 0;
+    h->begun = true; h->finalized = false; h->restored = false; h->steps_done = 0; h->sim_launches = 0;
     return PPP_OK;
 }
 
@@ -466,6 +464,13 @@ ppp_status do_advance(ppp_handle *h, int64_t n, hipStream_t st) {
 
 ppp_status do_finalize(ppp_handle *h, hipStream_t st) {
     if (!h->begun) return fail(h, PPP_E_STATE, "finalize before begin");
+    if (h->steps_done == 0 && !h->restored) {
+        // no step was taken: still build the initial state and empty accumulators
+        for (auto &ph : h->probs) {
+            ppp_status s = launch_items(h, ph, 0, 0, st, nullptr, -1, ph.first_item, ph.n_items);
+            if (s != PPP_OK) return s;
+        }
+    }
     HIPCHK(h, hipEventRecord(h->ev[2], st));
     HIPCHK(h, launch_reduce(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_blocks, st));
     HIPCHK(h, launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, st));
@@ -765,7 +770,7 @@ ppp_status ppp_restore(ppp_handle *h, void *ws, size_t ws_bytes, const void *hos
     HIPCHK(h, hipStreamSynchronize(st));
     HIPCHK(h, hipEventRecord(h->ev[1], st));
     std::memcpy(&h->steps_done, p + 8, 8);
-    h->begun = true; h->finalized = false; h->sim_launches = 0;
+    h->begun = true; h->finalized = false; h->restored = true; h->sim_launches = 0;
     return PPP_OK;
 }
 

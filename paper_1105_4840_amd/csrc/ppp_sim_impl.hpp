@@ -394,11 +394,11 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre_at(P, lam_w, step_begin), px, py, pz, fx, fy, fz, nullptr);
 
     const T h = (T)(0.5 * P.dt);
+    const T c1 = (T)P.c1;
     const T hm = (T)(0.5 * P.dt * P.inv_mass);
-    const T c1 = (T)P.c1, c2sd = (T)P.c2sd;
+    const T c2sd = (T)P.c2sd;
     for (int64_t n = step_begin + 1; n <= n_end; ++n) {
         if (!alive) break;
-        // B, A, O, A on the mobile beads (bead 0 and padding stay put)
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = i0 + b;

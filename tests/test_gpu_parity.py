@@ -242,3 +242,43 @@ def test_fp32_chain_statistics_match_oracle():
     for key in ("dF_je", "dF_fluct", "dF_gauss"):
         se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
         assert abs(res[key][-1] - ref[key][-1]) < 3.5 * se, (key, res[key][-1], ref[key][-1], se)
+
+
+def _shapes():
+    from paper_1105_4840_amd import build
+    return build.shapes()
+
+
+@pytest.mark.parametrize("shape", _shapes(), ids=lambda s: f"{s[0]}x{s[1]}")
+def test_every_kernel_shape_fp64_trajectory_and_forces(shape, tmp_path, monkeypatch):
+    """Each compiled (lanes x beads-per-lane) shape, forced through the shape table:
+    fp64 100-step trajectory within 1e-10 and fp32 forces within 1e-5 of the oracle."""
+    G, B = shape
+    n = max(2, G * B - (B // 2))          # leaves some padding beads in the last lane
+    _say(f"case shape {G}x{B} N={n}")
+    table = tmp_path / "tune.txt"
+    table.write_text(f"{n} 1 {G} {B}\n{n} 0 {G} {B}\n")
+    monkeypatch.setenv("PPP_TUNE_TABLE", str(table))
+    prob = ppp_inputs.config_chain_small(n, n_replicas=6, n_steps=100, n_windows=3, precision="fp64")
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        tr = ppp.ppp_trajectory(h, ws, 2, 5, 100, 3 * n).cpu().numpy()
+    finally:
+        ppp.ppp_destroy(h)
+    ref = oracle.trajectory(prob, 2, 5, 100)
+    assert np.max(np.abs(tr - ref)) < 1e-10, np.max(np.abs(tr - ref))
+    p32 = dict(prob, precision="fp32")
+    conf = ppp_inputs.random_chain_coords(n, 3, seed=G * 100 + B)
+    h = ppp.ppp_create(p32)
+    try:
+        ws = ppp.workspace(h)
+        x = torch.tensor(conf.reshape(len(conf), -1), dtype=torch.float64, device="cuda")
+        f, e = ppp.ppp_eval_forces(h, ws, x, 0.4 * n)
+        f = f.cpu().numpy().reshape(len(conf), -1, 3)
+    finally:
+        ppp.ppp_destroy(h)
+    for c in range(len(conf)):
+        xc = conf[c].astype(np.float32).astype(np.float64)
+        _, _, fr = oracle.chain_forces(p32, xc, 0.4 * n)
+        assert np.linalg.norm(f[c, 1:] - fr[1:]) <= 1e-5 * np.linalg.norm(fr[1:])
