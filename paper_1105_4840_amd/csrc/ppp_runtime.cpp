@@ -19,6 +19,7 @@
 #include "ppp.h"
 #include "ppp_internal.hpp"
 #include "ppp_launch.hpp"
+#include "ppp_shapes.hpp"
 
 using namespace ppp;
 
@@ -617,11 +618,7 @@ static ppp_status batch_capture(ppp_handle *h) {
     HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     int *tickets = reinterpret_cast<int *>(h->ws + h->off_tickets);
     hipError_t e = launch_init(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_k, h->max_m, tickets, 64, h->cap);
-    // step-0 initialisation of every item, per shape group (direct launch)
-    for (size_t gi = 0; gi < h->groups.size() && e == hipSuccess; ++gi) {
-        const VariantGroup &g = h->groups[gi];
-        e = launch_sim(d_probs(h), d_items(h) + g.first_item, g.n_items, h->ws, 0, 0, PPP_MODEL_CHAIN, g.precision, g.G, g.B, nullptr, -1, h->cap);
-    }
+    // the persistent kernels start every item at step 0, where its initial state is built
     if (e == hipSuccess) e = hipEventRecord(h->side_ev[0], h->cap);
     for (size_t gi = 0; gi < h->groups.size() && e == hipSuccess; ++gi) {
         const VariantGroup &g = h->groups[gi];
@@ -822,6 +819,78 @@ ppp_status ppp_trajectory(ppp_handle *h, void *ws, size_t bytes, int32_t window,
     if ((s = launch_items(h, ph, 0, n_steps, st, d_out, gid, item, 1)) != PPP_OK) return s;
     h->begun = false; h->finalized = false;
     return PPP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: for each chain-length bucket, time every compiled shape that holds
+// the chain on a synthetic problem sized to fill the GPU, keep the fastest.
+// ---------------------------------------------------------------------------
+ppp_status ppp_autotune(const char *path, void *ws, size_t bytes, void *stream) {
+    if (!path || !ws) return PPP_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    static const int kBuckets[] = {4, 8, 10, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    static const int kShapes[][2] = {
+#define PPP_LIST(GG, BB) {GG, BB},
+        PPP_FOR_EACH_SHAPE_RT(PPP_LIST)
+#undef PPP_LIST
+    };
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return PPP_E_DEVICE;
+    std::ostringstream table;
+    table << "# nmax precision lanes beads_per_lane   (ppp_autotune: fastest measured shape per chain length)\n";
+    ppp_status result = PPP_OK;
+    for (int prec = 0; prec <= 1 && result == PPP_OK; ++prec) {
+        for (int N : kBuckets) {
+            double best = 1e300; int bG = 0, bB = 0;
+            for (const auto &sh : kShapes) {
+                const int G = sh[0], B = sh[1];
+                if (G * B < N || G * B > 4 * N + 8) continue;
+                std::vector<double> lam(8);
+                for (int i = 0; i < 8; ++i) lam[i] = 0.35 * (N - 1) + 0.05 * i;
+                ppp_problem p{};
+                p.model = PPP_MODEL_CHAIN;
+                p.chain = ppp_chain{N, 100.0, 1.0, 5.0, 1.0, 1.0, 2.5, 0, 1.0, 1.0};
+                p.n_windows = 8; p.lambda = lam.data();
+                p.k = 20.0; p.kT = 1.0; p.dt = 0.005;
+                p.n_steps = N >= 256 ? 60 : (N >= 64 ? 200 : 600);
+                p.n_equil = p.n_steps / 2; p.sample_every = 10;
+                // enough replicas for about eight waves per SIMD of the whole chip
+                const int64_t lanes = (int64_t)cus * 4 * 64 * 8;
+                p.n_replicas = (int)std::max<int64_t>(64, std::min<int64_t>(16384, lanes / G / 8));
+                if (N >= 256) p.n_replicas = std::min(p.n_replicas, 2048);
+                p.seed = 7; p.precision = (ppp_precision)prec;
+                p.xi_min = 0.0; p.xi_bin = 0.01 * N; p.xi_nbins = 128; p.w_half_bins = 0; p.n_jack_blocks = 8;
+                ppp_handle *h = new ppp_handle();
+                h->probs.resize(1);
+                std::string msg;
+                std::vector<TuneEntry> force{TuneEntry{N, prec, G, B}};
+                if (build_problem(&p, h->probs[0], force, msg) != PPP_OK || h->probs[0].G != G || h->probs[0].B != B) { delete h; continue; }
+                make_items(h->probs[0], 0, h->items);
+                finish_layout(h);
+                if (h->ws_bytes > (int64_t)bytes) { delete h; continue; }
+                ppp_status s2 = do_begin(h, ws, bytes, st);
+                if (s2 == PPP_OK && hipEventRecord(e0, st) != hipSuccess) s2 = PPP_E_DEVICE;
+                if (s2 == PPP_OK) s2 = do_advance(h, p.n_steps, st);
+                if (s2 == PPP_OK && hipEventRecord(e1, st) != hipSuccess) s2 = PPP_E_DEVICE;
+                if (s2 == PPP_OK && hipEventSynchronize(e1) != hipSuccess) s2 = PPP_E_DEVICE;
+                if (s2 != PPP_OK) { ppp_destroy(h); result = s2; break; }
+                const double t = ev_ms(e0, e1) / ((double)p.n_windows * p.n_replicas * p.n_steps);
+                ppp_destroy(h);
+                if (t < best) { best = t; bG = G; bB = B; }
+            }
+            if (result != PPP_OK) break;
+            if (bG > 0) table << N << " " << prec << " " << bG << " " << bB << "   # " << best * 1e6 << " ns per replica-step\n";
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != PPP_OK) return result;
+    std::ofstream f(path);
+    if (!f) return PPP_E_INVALID_ARG;
+    f << table.str();
+    return f ? PPP_OK : PPP_E_INVALID_ARG;
 }
 
 ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n, uint32_t *d_words,

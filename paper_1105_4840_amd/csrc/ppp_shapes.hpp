@@ -4,3 +4,6 @@
 #define PPP_FOR_EACH_SHAPE(X)                                                                     \
     X(1, 4) X(1, 8) X(1, 12) X(1, 16) X(2, 5) X(2, 8) X(4, 3) X(4, 4) X(4, 8) X(8, 2) X(8, 4) \
     X(8, 8) X(16, 2) X(16, 4) X(16, 8) X(32, 2) X(32, 4) X(32, 8) X(64, 2) X(64, 4) X(64, 8)
+
+// the same list for host-only code
+#define PPP_FOR_EACH_SHAPE_RT(X) PPP_FOR_EACH_SHAPE(X)

@@ -112,3 +112,7 @@ def test_batch_rejects_1d():
     h = ppp.ppp_batch_create(ppp_inputs.batched_instances(6, seed=3))
     assert ppp.ppp_workspace_size(h) > 0
     ppp.ppp_destroy(h)
+
+
+def test_autotune_rejects_null_path():
+    assert ppp.lib().ppp_autotune(None, None, 0, None) == ppp.PPP_E_INVALID_ARG
