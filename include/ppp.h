@@ -264,25 +264,40 @@ ppp_status ppp_mlp_grad(const float *d_params, const float *d_t, const float *d_
 ppp_status ppp_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, float lr,
                         int32_t step, void *hip_stream);
 
-/* Adaptive protocol: rounds of (run the new windows, train the surrogate on
- * all window data, place new windows where adjacent windows overlap too
- * little), within a budget of replica-steps.  The answer is always the plain
- * JE profile (Eq. 12) over the simulated windows.  */
+/* Adaptive protocol with learned window placement.  Exploration rounds run
+ * short protocols (explore_replicas replicas, explore_steps steps) on new
+ * windows; the surrogate is trained on the GPU on every explored window's
+ * slope F'(lambda_i) = k (lambda_i - <x_i>) (Eq. 14 read as thermodynamic
+ * integration, Sec. V) and on the JE increments of Eq. 12 between adjacent
+ * explored windows (weighted by their Kish effective-sample fraction); its
+ * curvature gives sigma(lambda)^2 = (k - F''(lambda)) / (beta k^2), the width
+ * of the xi distribution at lambda, and windows are placed so that
+ * |dlambda| / sigma(lambda) = target_dl_over_sigma, the adjacent-overlap
+ * criterion of Sec. IV B and Sec. V.  Windows the surrogate predicts but no
+ * round has explored are explored next.  Then one production run of the
+ * protocol on the placed windows uses the rest of the budget (base's
+ * n_replicas, steps = remaining budget / (windows x replicas)).  The answer is
+ * that run's plain profiles; uniform windows are the fallback when the
+ * surrogate fails to train.  */
 typedef struct {
-    int64_t budget_replica_steps;   /* total over all rounds */
+    int64_t budget_replica_steps;   /* exploration + production */
     int32_t initial_windows;        /* round-0 uniform windows (>= 2) */
     int32_t max_rounds, max_windows;
-    double target_dl_over_sigma;    /* wanted |dlambda_i| / sigma_i between neighbours */
-    int32_t train_iters;
+    double target_dl_over_sigma;    /* wanted |dlambda_i| / sigma between neighbours (> 0) */
+    int32_t train_iters;            /* Adam steps per round */
     double lr;
-    uint64_t init_seed;             /* MLP initialisation */
+    uint64_t init_seed;             /* surrogate initialisation */
+    int32_t explore_replicas;       /* replicas per exploration window (0: n_replicas / 8) */
+    int64_t explore_steps;          /* steps per exploration window (0: n_steps / 4) */
+    int64_t min_production_steps;   /* fail (PPP_E_INVALID_ARG) if the production run would be shorter */
 } ppp_adaptive;
 
-/* base describes the system, lambda range [lambda[0], lambda[n_windows-1]],
- * replicas and steps per window (n_steps of every window of every round);
- * lambda_out (host, capacity max_windows) and *n_windows_out receive the
- * final windows, out the result on them (sized for max_windows).
- * d_workspace: at least ppp_adaptive_workspace_size bytes. */
+/* base describes the system, the lambda range [lambda[0], lambda[n_windows-1]],
+ * replicas and the other run settings; lambda_out (host, capacity
+ * max_windows) and *n_windows_out receive the production windows, out the
+ * production run's results (buffers sized for max_windows), and
+ * *replica_steps_used the total spent.  d_workspace: at least
+ * ppp_adaptive_workspace_size bytes. */
 ppp_status ppp_adaptive_workspace_size(const ppp_problem *base, const ppp_adaptive *a, size_t *bytes);
 ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void *d_workspace,
                             size_t bytes, void *hip_stream, double *lambda_out,

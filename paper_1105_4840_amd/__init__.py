@@ -80,7 +80,8 @@ class ppp_adaptive(ctypes.Structure):
     _fields_ = [("budget_replica_steps", ctypes.c_int64), ("initial_windows", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("max_windows", ctypes.c_int32),
                 ("target_dl_over_sigma", ctypes.c_double), ("train_iters", ctypes.c_int32),
-                ("lr", ctypes.c_double), ("init_seed", ctypes.c_uint64)]
+                ("lr", ctypes.c_double), ("init_seed", ctypes.c_uint64), ("explore_replicas", ctypes.c_int32),
+                ("explore_steps", ctypes.c_int64), ("min_production_steps", ctypes.c_int64)]
 
 
 _lib = None
@@ -339,6 +340,41 @@ def ppp_philox(seed, c0, c1, c2, c3, n, device="cuda", stream=None):
     st = lib().ppp_philox(int(seed), c0, c1, c2, c3, int(n), _ptr(words), _ptr(z64), _ptr(z32), _stream(stream))
     _check(st, None, "ppp_philox")
     return words.cpu().numpy().view(np.uint32), z64.cpu().numpy(), z32.cpu().numpy()
+
+
+def ppp_adaptive_run(base: dict, adaptive: dict, stream=None, device="cuda"):
+    """Adaptive protocol with learned window placement; returns (results dict on the
+    production windows, lambda array, replica-steps used)."""
+    import torch
+    p, keep = make_problem(base)
+    a = ppp_adaptive(int(adaptive["budget_replica_steps"]), int(adaptive.get("initial_windows", 11)),
+                     int(adaptive.get("max_rounds", 4)), int(adaptive.get("max_windows", 256)),
+                     float(adaptive.get("target_dl_over_sigma", 1.0)), int(adaptive.get("train_iters", 400)),
+                     float(adaptive.get("lr", 3e-3)), int(adaptive.get("init_seed", 1)),
+                     int(adaptive.get("explore_replicas", 0)), int(adaptive.get("explore_steps", 0)),
+                     int(adaptive.get("min_production_steps", 0)))
+    n = ctypes.c_size_t()
+    _check(lib().ppp_adaptive_workspace_size(ctypes.byref(p), ctypes.byref(a), ctypes.byref(n)), None,
+           "ppp_adaptive_workspace_size")
+    ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=device)
+    smax = int(a.max_windows)
+    shaped = dict(base, **{"lambda": np.zeros(smax)})
+    r, bufs = _result_buffers(shaped)
+    lam = np.zeros(smax)
+    nw = ctypes.c_int32()
+    used = ctypes.c_int64()
+    st = lib().ppp_adaptive_run(ctypes.byref(p), ctypes.byref(a), _ptr(ws), ws.numel(), _stream(stream),
+                                lam.ctypes.data_as(_dp), ctypes.byref(nw), ctypes.byref(used), ctypes.byref(r))
+    _check(st, None, "ppp_adaptive_run")
+    s = int(nw.value)
+    out = {}
+    for key, v in bufs.items():
+        if isinstance(v, np.ndarray) and v.ndim >= 1 and v.shape[0] in (smax, smax - 1):
+            out[key] = v[:s] if v.shape[0] == smax else v[:s - 1]
+        else:
+            out[key] = v
+    out["status"] = st
+    return out, lam[:s], int(used.value)
 
 
 def run(prob: dict, stream=None, device="cuda"):

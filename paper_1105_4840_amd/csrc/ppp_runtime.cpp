@@ -18,6 +18,7 @@
 
 #include "ppp.h"
 #include "ppp_internal.hpp"
+#include "ppp_internal_api.hpp"
 #include "ppp_launch.hpp"
 #include "ppp_shapes.hpp"
 
@@ -901,3 +902,18 @@ ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Internal entry points for the adaptive protocol (ppp_adaptive.cpp).
+// ===========================================================================
+namespace ppp {
+
+size_t workspace_bytes_for(const ppp_problem *p) {
+    ppp_handle *h = nullptr;
+    if (ppp_create(p, &h) != PPP_OK) return 0;
+    const size_t n = (size_t)h->ws_bytes;
+    ppp_destroy(h);
+    return n;
+}
+
+}  // namespace ppp
