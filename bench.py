@@ -65,6 +65,50 @@ def cpu_baseline(prob, target_seconds):
                       f"({rs:.3g} replica-steps, {el:.1f} s, fp64 C, OpenMP over replicas)"}
 
 
+def placement_study(args):
+    """dF error at equal budget, 32-bead chain, windows in [3, 28]: 21 uniform windows at
+    2e9 replica-steps against learned placement at half (and at the full) budget; the
+    reference is a dense, long run (201 windows, 40000 steps)."""
+    import numpy as np
+    import paper_1105_4840_amd as ppp
+    import ppp_inputs
+
+    def err(res, lam, ref_lam, ref):
+        out = {}
+        for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com"):
+            f = np.interp(lam, ref_lam, ref["dF_je"])
+            out[key + "_end"] = float(abs(res[key][-1] - ref["dF_je"][-1]))
+            out[key + "_rms"] = float(np.sqrt(np.mean((res[key] - f) ** 2)))
+        out["dF_je_se_end"] = float(res["dF_je_se"][-1])
+        return out
+
+    t0 = time.time()
+    ref_p = ppp_inputs.config_chain32(n_windows=201, n_steps=args.ref_steps)
+    ref, _ = ppp.run(ref_p)
+    ref_lam = np.array(ref_p["lambda"])
+    print(f"# reference: 201 windows x 4096 x {args.ref_steps} steps, {time.time() - t0:.1f} s, "
+          f"dF_je(28) = {ref['dF_je'][-1]:.3f} +- {ref['dF_je_se'][-1]:.3f}", file=sys.stderr, flush=True)
+    uni_p = ppp_inputs.config_chain32()
+    uni, _ = ppp.run(uni_p)
+    budget = 21 * 4096 * 23251
+    rows = {"uniform_21": dict(err(uni, np.array(uni_p["lambda"]), ref_lam, ref), replica_steps=budget, windows=21)}
+    for frac in (0.5, 1.0):
+        base = ppp_inputs.config_chain32(n_steps=4000)
+        ad = {"budget_replica_steps": int(frac * budget), "initial_windows": 11, "max_rounds": 5, "max_windows": 256,
+              "target_dl_over_sigma": 1.0, "train_iters": 800, "lr": 3e-3, "init_seed": 1,
+              "explore_replicas": 256, "explore_steps": 2000, "min_production_steps": args.min_steps}
+        res, lam, used = ppp.ppp_adaptive_run(base, ad)
+        rows[f"learned_{frac:g}budget"] = dict(err(res, lam, ref_lam, ref), replica_steps=used, windows=len(lam),
+                                               dl_over_sigma_max=float(np.nanmax(res["dlambda_over_sigma"])))
+        print(f"# learned at {frac:g} budget: {len(lam)} windows, {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    rows["uniform_21"]["dl_over_sigma_max"] = float(np.nanmax(uni["dlambda_over_sigma"]))
+    print(json.dumps({"study": "dF abs error (kT) at equal budget, 32-bead chain, lambda in [3, 28]",
+                      "reference": {"windows": 201, "steps": args.ref_steps, "dF_je_end": float(ref["dF_je"][-1]),
+                                    "dF_je_se_end": float(ref["dF_je_se"][-1]),
+                                    "dF_fluct_end": float(ref["dF_fluct"][-1]), "dF_gauss_end": float(ref["dF_gauss"][-1])},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +118,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="advance in chunks of this many steps (progress lines)")
+    ap.add_argument("--placement-study", action="store_true",
+                    help="dF error at equal budget, uniform vs learned windows (32-bead chain)")
+    ap.add_argument("--ref-steps", type=int, default=40000)
+    ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
+    ap.add_argument("--pmc-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the protocol on one GPU; --gpus must be 1 "
@@ -85,6 +135,10 @@ def main():
     import paper_1105_4840_amd as ppp
     import ppp_inputs
 
+    if args.placement_study:
+        torch.cuda.set_device(0)
+        placement_study(args)
+        return
     fn, desc = WORKLOADS[args.workload]
     prob = getattr(ppp_inputs, fn)()
     torch.cuda.set_device(0)
@@ -106,6 +160,12 @@ def main():
         else:
             ppp.ppp_run(h, ws, stream)
 
+    if args.pmc_copy_mib > 0:
+        src = torch.ones(args.pmc_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         one_run()
     torch.cuda.synchronize()

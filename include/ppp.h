@@ -275,10 +275,13 @@ ppp_status ppp_mlp_adam(float *d_params, const float *d_grad, float *d_m, float 
  * |dlambda| / sigma(lambda) = target_dl_over_sigma, the adjacent-overlap
  * criterion of Sec. IV B and Sec. V.  Windows the surrogate predicts but no
  * round has explored are explored next.  Then one production run of the
- * protocol on the placed windows uses the rest of the budget (base's
- * n_replicas, steps = remaining budget / (windows x replicas)).  The answer is
- * that run's plain profiles; uniform windows are the fallback when the
- * surrogate fails to train.  */
+ * protocol on the placed windows uses the rest of the budget: base's
+ * n_replicas and steps = remaining budget / (windows x replicas), unless that
+ * is below min_production_steps, in which case the replicas per window are
+ * reduced (not below 16) so every window relaxes at least that long (the
+ * relaxation time decides the accuracy, Sec. IV D).  The answer is that run's
+ * plain profiles; uniform windows are the fallback when the surrogate fails
+ * to train.  Exploration uses at most half of the budget.  */
 typedef struct {
     int64_t budget_replica_steps;   /* exploration + production */
     int32_t initial_windows;        /* round-0 uniform windows (>= 2) */
@@ -289,7 +292,8 @@ typedef struct {
     uint64_t init_seed;             /* surrogate initialisation */
     int32_t explore_replicas;       /* replicas per exploration window (0: n_replicas / 8) */
     int64_t explore_steps;          /* steps per exploration window (0: n_steps / 4) */
-    int64_t min_production_steps;   /* fail (PPP_E_INVALID_ARG) if the production run would be shorter */
+    int64_t min_production_steps;   /* relaxation steps every production window gets (see above);
+                                       PPP_E_INVALID_ARG if the budget cannot afford them */
 } ppp_adaptive;
 
 /* base describes the system, the lambda range [lambda[0], lambda[n_windows-1]],

@@ -285,10 +285,20 @@ ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void
         for (int i = 0; i < a->initial_windows; ++i) placed[i] = lo + (hi - lo) * i / (a->initial_windows - 1);
     }
     // ---- production run on the placed windows with the remaining budget ----
-    const int64_t per_step = (int64_t)placed.size() * base->n_replicas;
-    const int64_t steps = (a->budget_replica_steps - used) / per_step;
+    // every window keeps at least min_production_steps of relaxation (Sec. IV D: the
+    // relaxation time decides the accuracy); replicas give way first, down to 16
+    const int64_t left = a->budget_replica_steps - used;
+    const int64_t W = (int64_t)placed.size();
+    int32_t R = base->n_replicas;
+    int64_t steps = left / (W * R);
+    if (steps < a->min_production_steps) {
+        R = (int32_t)std::max<int64_t>(16, left / (W * std::max<int64_t>(1, a->min_production_steps)));
+        R = std::min(R, base->n_replicas);
+        steps = left / (W * R);
+    }
     if (steps < std::max<int64_t>(2, a->min_production_steps)) return PPP_E_INVALID_ARG;
-    s = run_windows(base, placed, base->n_replicas, steps, ws, run_bytes, st, out, nullptr);
+    const int64_t per_step = W * R;
+    s = run_windows(base, placed, R, steps, ws, run_bytes, st, out, nullptr);
     if (s != PPP_OK && s != PPP_E_NUMERICAL) return s;
     used += per_step * steps;
     for (size_t i = 0; i < placed.size(); ++i) lambda_out[i] = placed[i];
