@@ -79,7 +79,7 @@ typedef struct {
     double mass, gamma;
 } ppp_chain;
 
-#define PPP_MAX_BEADS 512
+#define PPP_MAX_BEADS 256
 
 typedef struct {
     ppp_model model;

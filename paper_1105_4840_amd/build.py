@@ -50,11 +50,25 @@ def _compile(src):
     path = src if os.path.isabs(src) else os.path.join(CSRC, src)
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     lang = ["-x", "hip"]
-    cmd = ["hipcc", *lang, *COMMON, "-c", path, "-o", obj]
+    cmd = ["hipcc", *lang, *COMMON, "-Rpass-analysis=kernel-resource-usage", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj, r.stderr
+
+
+def _scratch_users(stderr):
+    """Kernels of one translation unit that need scratch (spilled registers)."""
+    bad, name = [], None
+    for line in stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0 and "sim_" in name:
+            bad.append((name, int(m.group(1))))
+    return bad
 
 
 def build(verbose: bool = False) -> str:
@@ -64,10 +78,15 @@ def build(verbose: bool = False) -> str:
     jobs = int(os.environ.get("PPP_BUILD_JOBS", "8"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
         results = list(ex.map(_compile, srcs))
+    spills = [b for _, err in results for b in _scratch_users(err)]
+    if spills:
+        raise RuntimeError("simulation kernels spill to scratch (drop the shape from ppp_shapes.hpp): "
+                           + ", ".join(f"{n} {b} B/lane" for n, b in spills))
     if verbose:
         for _, err in results:
-            if err.strip():
-                print(err, file=sys.stderr)
+            lines = [l for l in err.splitlines() if "remark" not in l and "Rpass" not in l and l.strip()]
+            if lines:
+                print("\n".join(lines), file=sys.stderr)
     objs = [o for o, _ in results]
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

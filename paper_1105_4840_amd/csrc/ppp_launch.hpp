@@ -8,13 +8,15 @@
 namespace ppp {
 
 bool chain_shape_supported(int G, int B);
-int sim_blocks_per_cu(int precision, int G, int B);  // resident workgroups of the persistent kernel
+int sim_blocks_per_cu(int precision, int G, int B, int lds_cap);  // resident workgroups of the persistent kernel
+// workgroup-private xi histograms: up to this many bins live in LDS (else counts go straight to memory)
+constexpr int kLdsHistCap = 16384;
 
 hipError_t launch_sim(const DevProblem *d_probs, const WorkItem *d_items, int n_items, char *ws, int64_t step_begin,
                       int64_t step_end, int model, int precision, int G, int B, double *traj, int64_t traj_rep,
-                      hipStream_t stream);
+                      int lds_cap, hipStream_t stream);
 hipError_t launch_sim_persistent(const DevProblem *d_probs, const WorkItem *d_items, int n_items, int *d_ticket,
-                                 char *ws, int precision, int G, int B, int n_groups, hipStream_t stream);
+                                 char *ws, int precision, int G, int B, int n_groups, int lds_cap, hipStream_t stream);
 hipError_t launch_eval(const DevProblem *d_probs, const double *coords, int n_rep, double centre, double *forces,
                        double *energy, int model, int precision, int G, int B, hipStream_t stream);
 hipError_t launch_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int n, uint32_t *words,

@@ -157,18 +157,27 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
 }
 
 // Kernel shape (lanes per replica G, beads per lane B) for a chain length.
-void default_shape(int N, int &G, int &B) {
+void default_shape(int N, int precision, int &G, int &B) {
     // measured on MI355X: short chains want a few lanes per replica to fill the
-    // chip; long chains want more beads per lane for fewer rotation rounds
+    // chip, long chains more beads per lane for fewer rotation rounds; fp64 (twice
+    // the registers) keeps two beads per lane so that nothing spills
+    if (precision == PPP_FP64) {
+        if (N <= 4) { G = 1; B = 4; }
+        else if (N <= 16) { G = 8; B = 2; }
+        else if (N <= 32) { G = 16; B = 2; }
+        else if (N <= 64) { G = 32; B = 2; }
+        else if (N <= 128) { G = 64; B = 2; }
+        else { G = 64; B = 4; }
+        return;
+    }
     if (N <= 4) { G = 1; B = 4; }
     else if (N <= 8) { G = 1; B = 8; }
     else if (N <= 10) { G = 2; B = 5; }
-    else if (N <= 16) { G = 2; B = 8; }
+    else if (N <= 16) { G = 4; B = 4; }
     else if (N <= 32) { G = 16; B = 2; }
     else if (N <= 64) { G = 16; B = 4; }
-    else if (N <= 128) { G = 16; B = 8; }
-    else if (N <= 256) { G = 64; B = 4; }
-    else { G = 64; B = 8; }
+    else if (N <= 128) { G = 32; B = 4; }
+    else { G = 64; B = 4; }
 }
 
 struct TuneEntry { int nmax, precision, G, B; };
@@ -189,7 +198,7 @@ std::vector<TuneEntry> read_tune_table(const char *path) {
 }
 
 void choose_shape(int N, int precision, const std::vector<TuneEntry> &tune, int &G, int &B) {
-    default_shape(N, G, B);
+    default_shape(N, precision, G, B);
     for (const auto &e : tune)
         if (e.precision == precision && N <= e.nmax && e.G * e.B >= N && chain_shape_supported(e.G, e.B) &&
             (e.G == 1 || e.B >= 2)) {
@@ -355,8 +364,9 @@ ppp_status ensure_events(ppp_handle *h) {
 
 ppp_status launch_items(ppp_handle *h, const ProblemHost &ph, int64_t b, int64_t e, hipStream_t st, double *traj,
                         int64_t traj_rep, int first, int count) {
+    const int cap = ph.dev.xi_nbins <= kLdsHistCap ? ph.dev.xi_nbins : 0;
     HIPCHK(h, launch_sim(d_probs(h), d_items(h) + first, count, h->ws, b, e, ph.dev.model, ph.dev.precision, ph.G,
-                         ph.B, traj, traj_rep, st));
+                         ph.B, traj, traj_rep, cap, st));
     return PPP_OK;
 }
 
@@ -624,9 +634,13 @@ static ppp_status batch_capture(ppp_handle *h) {
     for (size_t gi = 0; gi < h->groups.size() && e == hipSuccess; ++gi) {
         const VariantGroup &g = h->groups[gi];
         e = hipStreamWaitEvent(h->side[gi], h->side_ev[0], 0);
-        const int per_cu = std::max(1, sim_blocks_per_cu(g.precision, g.G, g.B));
+        int kmax = 0;
+        for (auto &ph : h->probs)
+            if (ph.dev.precision == g.precision && ph.G == g.G && ph.B == g.B) kmax = std::max(kmax, ph.dev.xi_nbins);
+        const int cap = kmax <= kLdsHistCap ? kmax : 0;
+        const int per_cu = std::max(1, sim_blocks_per_cu(g.precision, g.G, g.B, cap));
         const int groups = std::min(g.n_items, std::max(1, per_cu * cus));
-        if (e == hipSuccess) e = launch_sim_persistent(d_probs(h), d_items(h) + g.first_item, g.n_items, tickets + gi, h->ws, g.precision, g.G, g.B, groups, h->side[gi]);
+        if (e == hipSuccess) e = launch_sim_persistent(d_probs(h), d_items(h) + g.first_item, g.n_items, tickets + gi, h->ws, g.precision, g.G, g.B, groups, cap, h->side[gi]);
         if (e == hipSuccess) e = hipEventRecord(h->side_ev[gi + 1], h->side[gi]);
         if (e == hipSuccess) e = hipStreamWaitEvent(h->cap, h->side_ev[gi + 1], 0);
     }

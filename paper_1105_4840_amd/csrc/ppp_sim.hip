@@ -20,19 +20,19 @@ __global__ void philox_blocks(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t 
 
 #define PPP_DECLARE(GG, BB)                                                                                         \
     extern template hipError_t launch_chain_direct<float, GG, BB>(const DevProblem *, const WorkItem *, int, char *, \
-                                                                  int64_t, int64_t, double *, int64_t, hipStream_t); \
+                                                                  int64_t, int64_t, double *, int64_t, int, hipStream_t); \
     extern template hipError_t launch_chain_direct<double, GG, BB>(const DevProblem *, const WorkItem *, int, char *, \
-                                                                   int64_t, int64_t, double *, int64_t, hipStream_t); \
+                                                                   int64_t, int64_t, double *, int64_t, int, hipStream_t); \
     extern template hipError_t launch_chain_persistent<float, GG, BB>(const DevProblem *, const WorkItem *, int, int *, \
-                                                                      char *, int, hipStream_t);                   \
+                                                                      char *, int, int, hipStream_t);              \
     extern template hipError_t launch_chain_persistent<double, GG, BB>(const DevProblem *, const WorkItem *, int, int *, \
-                                                                       char *, int, hipStream_t);                  \
+                                                                       char *, int, int, hipStream_t);             \
     extern template hipError_t launch_chain_eval<float, GG, BB>(const DevProblem *, const double *, int, double, double *, \
                                                                 double *, hipStream_t);                            \
     extern template hipError_t launch_chain_eval<double, GG, BB>(const DevProblem *, const double *, int, double, double *, \
                                                                  double *, hipStream_t);                           \
-    extern template int chain_blocks_per_cu<float, GG, BB>();                                                      \
-    extern template int chain_blocks_per_cu<double, GG, BB>();
+    extern template int chain_blocks_per_cu<float, GG, BB>(int);                                                   \
+    extern template int chain_blocks_per_cu<double, GG, BB>(int);
 PPP_FOR_EACH_SHAPE(PPP_DECLARE)
 #undef PPP_DECLARE
 
@@ -43,9 +43,9 @@ bool chain_shape_supported(int G, int B) {
     return false;
 }
 
-int sim_blocks_per_cu(int precision, int G, int B) {
+int sim_blocks_per_cu(int precision, int G, int B, int lds_cap) {
 #define PPP_OCC(GG, BB) \
-    if (G == GG && B == BB) return precision == 1 ? chain_blocks_per_cu<double, GG, BB>() : chain_blocks_per_cu<float, GG, BB>();
+    if (G == GG && B == BB) return precision == 1 ? chain_blocks_per_cu<double, GG, BB>(lds_cap) : chain_blocks_per_cu<float, GG, BB>(lds_cap);
     PPP_FOR_EACH_SHAPE(PPP_OCC)
 #undef PPP_OCC
     return 1;
@@ -53,29 +53,30 @@ int sim_blocks_per_cu(int precision, int G, int B) {
 
 hipError_t launch_sim(const DevProblem *d_probs, const WorkItem *d_items, int n_items, char *ws, int64_t step_begin,
                       int64_t step_end, int model, int precision, int G, int B, double *traj, int64_t traj_rep,
-                      hipStream_t stream) {
+                      int lds_cap, hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
     if (model == 0) {
-        if (precision == 1) hipLaunchKernelGGL(sim_1d<double>, dim3(n_items), dim3(WG), 0, stream, d_probs, d_items, n_items, ws, step_begin, step_end, traj, (int)traj_rep);
-        else hipLaunchKernelGGL(sim_1d<float>, dim3(n_items), dim3(WG), 0, stream, d_probs, d_items, n_items, ws, step_begin, step_end, traj, (int)traj_rep);
+        const size_t sh = (size_t)lds_cap * 4;
+        if (precision == 1) hipLaunchKernelGGL(sim_1d<double>, dim3(n_items), dim3(WG), sh, stream, d_probs, d_items, n_items, ws, step_begin, step_end, traj, (int)traj_rep, lds_cap);
+        else hipLaunchKernelGGL(sim_1d<float>, dim3(n_items), dim3(WG), sh, stream, d_probs, d_items, n_items, ws, step_begin, step_end, traj, (int)traj_rep, lds_cap);
         return hipGetLastError();
     }
 #define PPP_LAUNCH(GG, BB)                                                                                              \
     if (G == GG && B == BB)                                                                                            \
-        return precision == 1 ? launch_chain_direct<double, GG, BB>(d_probs, d_items, n_items, ws, step_begin, step_end, traj, traj_rep, stream) \
-                              : launch_chain_direct<float, GG, BB>(d_probs, d_items, n_items, ws, step_begin, step_end, traj, traj_rep, stream);
+        return precision == 1 ? launch_chain_direct<double, GG, BB>(d_probs, d_items, n_items, ws, step_begin, step_end, traj, traj_rep, lds_cap, stream) \
+                              : launch_chain_direct<float, GG, BB>(d_probs, d_items, n_items, ws, step_begin, step_end, traj, traj_rep, lds_cap, stream);
     PPP_FOR_EACH_SHAPE(PPP_LAUNCH)
 #undef PPP_LAUNCH
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sim_persistent(const DevProblem *d_probs, const WorkItem *d_items, int n_items, int *d_ticket,
-                                 char *ws, int precision, int G, int B, int n_groups, hipStream_t stream) {
+                                 char *ws, int precision, int G, int B, int n_groups, int lds_cap, hipStream_t stream) {
     if (n_items <= 0) return hipSuccess;
 #define PPP_LAUNCH(GG, BB)                                                                                              \
     if (G == GG && B == BB)                                                                                            \
-        return precision == 1 ? launch_chain_persistent<double, GG, BB>(d_probs, d_items, n_items, d_ticket, ws, n_groups, stream) \
-                              : launch_chain_persistent<float, GG, BB>(d_probs, d_items, n_items, d_ticket, ws, n_groups, stream);
+        return precision == 1 ? launch_chain_persistent<double, GG, BB>(d_probs, d_items, n_items, d_ticket, ws, n_groups, lds_cap, stream) \
+                              : launch_chain_persistent<float, GG, BB>(d_probs, d_items, n_items, d_ticket, ws, n_groups, lds_cap, stream);
     PPP_FOR_EACH_SHAPE(PPP_LAUNCH)
 #undef PPP_LAUNCH
     return hipErrorInvalidValue;

@@ -33,9 +33,11 @@ __device__ __forceinline__ bool sample_now(const DevProblem &P, int64_t n) {
     return n > P.n_equil && ((n - P.n_equil) % P.sample_every) == 0;
 }
 
-// Folds one sample xi of window w into the replica's accumulator.
+// Folds one sample xi of window w into the replica's accumulator.  The
+// histogram count goes to the workgroup's LDS copy (lhist, all replicas of a
+// work item share one window) when there is one, else straight to memory.
 __device__ __forceinline__ void accumulate(const DevProblem &P, const double *lam, int w, double xi,
-                                           double *acc, unsigned long long *hist) {
+                                           double *acc, unsigned long long *hist, unsigned int *lhist) {
     const int s = P.n_windows;
     const double d = xi - lam[w];
     acc[A_N] += 1.0;
@@ -59,7 +61,23 @@ __device__ __forceinline__ void accumulate(const DevProblem &P, const double *la
     const double fb = floor((xi - P.xi_min) / P.xi_bin);
     if (fb < 0.0) acc[A_UNDER] += 1.0;
     else if (fb >= (double)P.xi_nbins) acc[A_OVER] += 1.0;
+    else if (lhist) atomicAdd(lhist + (int)fb, 1u);
     else atomicAdd(hist + (int64_t)w * P.xi_nbins + (int64_t)fb, 1ull);
+}
+
+// Workgroup-private histogram: cleared before an item, added to the window's
+// histogram in memory after it (one atomic per non-empty bin).
+__device__ __forceinline__ void lhist_clear(unsigned int *lhist, int K) {
+    for (int b = threadIdx.x; b < K; b += blockDim.x) lhist[b] = 0u;
+    __syncthreads();
+}
+__device__ __forceinline__ void lhist_flush(unsigned int *lhist, int K, unsigned long long *dst) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < K; b += blockDim.x) {
+        const unsigned int c = lhist[b];
+        if (c) atomicAdd(dst + b, (unsigned long long)c);
+    }
+    __syncthreads();
 }
 
 template <typename T> __device__ __forceinline__ T *state_ptr(char *ws, const DevProblem &P) {
@@ -80,15 +98,9 @@ __device__ __forceinline__ T force_1d(const DevProblem &P, T x, T centre) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
-                                             int n_items, char *__restrict__ ws, int64_t step_begin,
-                                             int64_t step_end, double *__restrict__ traj, int traj_rep) {
-    const int it = blockIdx.x;
-    if (it >= n_items) return;
-    const WorkItem item = items[it];
-    const DevProblem &P = probs[item.prob];
-    const int w = item.window;
-    const int rep = item.rep_begin + (int)threadIdx.x;
+__device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkItem &item, int w, int rep, char *ws,
+                                               int64_t step_begin, int64_t step_end, double *traj, int traj_rep,
+                                               unsigned int *lhist) {
     if ((int)threadIdx.x >= item.n_reps) return;
     const int64_t g = (int64_t)w * P.n_replicas + rep;
     const uint32_t gid = (uint32_t)g;
@@ -132,12 +144,30 @@ __global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ prob
         if (sample_now(P, n)) {
             const double xi = (double)x;
             if (!isfinite(xi) || fabs(xi) > P.xi_bound) { acc[A_BLOWN] = 1.0; alive = false; break; }
-            accumulate(P, lam, w, xi, acc, hist);
+            accumulate(P, lam, w, xi, acc, hist, lhist);
         }
     }
     for (int f = 0; f < A_NFIELDS; ++f) acc_g[f] = acc[f];
     st[0] = x; st[1] = eta_prev;
 }
+
+template <typename T>
+__global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
+                                             int n_items, char *__restrict__ ws, int64_t step_begin,
+                                             int64_t step_end, double *__restrict__ traj, int traj_rep, int lds_cap) {
+    extern __shared__ unsigned int s_hist[];
+    const int it = blockIdx.x;
+    if (it >= n_items) return;
+    const WorkItem item = items[it];
+    const DevProblem &P = probs[item.prob];
+    const int w = item.window;
+    const int rep = item.rep_begin + (int)threadIdx.x;
+    unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
+    if (lhist) lhist_clear(lhist, P.xi_nbins);
+    sim_1d_replica<T>(P, item, w, rep, ws, step_begin, step_end, traj, traj_rep, lhist);
+    if (lhist) lhist_flush(lhist, P.xi_nbins, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)w * P.xi_nbins);
+}
+
 
 // ===========================================================================
 // Chain model.
@@ -248,65 +278,68 @@ struct ChainForce {
             }
         }
 
-        // ---- bonded terms over a local window with a two-bead halo ----
-        T lx[L], ly[L], lz[L];
-#pragma unroll
-        for (int b = 0; b < B; ++b) { lx[HALO + b] = px[b]; ly[HALO + b] = py[b]; lz[HALO + b] = pz[b]; }
+        // ---- bonded terms: slide along the local beads [gB - HALO, gB + B + HALO) ----
+        // Two bond vectors are live at a time; each bond and angle that touches an
+        // owned bead adds its gradient straight to the owned beads (a lane recomputes
+        // the one or two terms it shares with a neighbour lane).
+        T hx[2 * HALO + 1], hy[2 * HALO + 1], hz[2 * HALO + 1];   // halo beads (prev lane's last two, next lane's first two)
         if constexpr (G > 1) {
             const int prev = gbase + (g > 0 ? g - 1 : 0);
             const int next = gbase + (g + 1 < G ? g + 1 : G - 1);
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                lx[h] = pull_f(prev, px[B - 2 + h]); ly[h] = pull_f(prev, py[B - 2 + h]); lz[h] = pull_f(prev, pz[B - 2 + h]);
-                lx[HALO + B + h] = pull_f(next, px[h]); ly[HALO + B + h] = pull_f(next, py[h]); lz[HALO + B + h] = pull_f(next, pz[h]);
+            for (int hh = 0; hh < 2; ++hh) {
+                hx[hh] = pull_f(prev, px[B - 2 + hh]); hy[hh] = pull_f(prev, py[B - 2 + hh]); hz[hh] = pull_f(prev, pz[B - 2 + hh]);
+                hx[HALO + hh] = pull_f(next, px[hh]); hy[HALO + hh] = pull_f(next, py[hh]); hz[HALO + hh] = pull_f(next, pz[hh]);
             }
         }
         const int ib = i0 - HALO;   // bead index of local slot 0
-        // bond vectors t -> t+1 for t = 0 .. L-2
-        T bx[L - 1], by[L - 1], bz[L - 1], bl[L - 1], bil[L - 1];
-#pragma unroll
-        for (int t = 0; t < L - 1; ++t) {
-            bx[t] = lx[t + 1] - lx[t]; by[t] = ly[t + 1] - ly[t]; bz[t] = lz[t + 1] - lz[t];
-            bl[t] = sqrt_t(bx[t] * bx[t] + by[t] * by[t] + bz[t] * bz[t]);
-            bil[t] = rcp_t(bl[t]);
-        }
         const T kb = (T)P.k_bond, r0 = (T)P.r0, kth = (T)P.k_angle;
-        // accumulate into local-window forces, then keep the owned part
-        T wx[L], wy[L], wz[L];
-#pragma unroll
-        for (int t = 0; t < L; ++t) { wx[t] = 0; wy[t] = 0; wz[t] = 0; }
+        // position of local slot t (compile-time t)
+        auto slot = [&](int t, T &x, T &y, T &z) {
+            if (t < HALO) { x = hx[t]; y = hy[t]; z = hz[t]; }
+            else if (t < HALO + B) { x = px[t - HALO]; y = py[t - HALO]; z = pz[t - HALO]; }
+            else { x = hx[t - B]; y = hy[t - B]; z = hz[t - B]; }
+        };
+        auto add = [&](int t, T gx_, T gy_, T gz_) {   // force on local slot t if it is owned
+            if (t >= HALO && t < HALO + B) { fx[t - HALO] += gx_; fy[t - HALO] += gy_; fz[t - HALO] += gz_; }
+        };
+        T ax = 0, ay = 0, az = 0, ail = 0;   // previous bond (t-1 -> t) and its inverse length
+        bool avalid = false;
 #pragma unroll
         for (int t = 0; t < L - 1; ++t) {
-            // bond (t, t+1) touches an owned bead?
-            if (t + 1 < HALO || t >= HALO + B) continue;
+            T x0, y0, z0, x1, y1, z1;
+            slot(t, x0, y0, z0);
+            slot(t + 1, x1, y1, z1);
+            const T bx = x1 - x0, by = y1 - y0, bz = z1 - z0;
+            const T bl = sqrt_t(bx * bx + by * by + bz * bz);
+            const T bil = rcp_t(bl);
             const int i = ib + t;
-            const bool valid = i >= 0 && i + 1 < N;
-            T gsc = kb * (bl[t] - r0) * bil[t];
-            gsc = valid ? gsc : (T)0;
-            wx[t] += gsc * bx[t]; wy[t] += gsc * by[t]; wz[t] += gsc * bz[t];
-            wx[t + 1] -= gsc * bx[t]; wy[t + 1] -= gsc * by[t]; wz[t + 1] -= gsc * bz[t];
-            if (ENERGY && valid && t >= HALO) e_bond += 0.5 * (double)(kb * (bl[t] - r0) * (bl[t] - r0));
+            const bool bvalid = i >= 0 && i + 1 < N;
+            // bond (t, t+1), k_b/2 (|b| - r0)^2: dU/db = k_b (|b| - r0) b/|b|
+            if (t + 1 >= HALO && t < HALO + B) {
+                T gsc = kb * (bl - r0) * bil;
+                gsc = bvalid ? gsc : (T)0;
+                add(t, gsc * bx, gsc * by, gsc * bz);
+                add(t + 1, -gsc * bx, -gsc * by, -gsc * bz);
+                if (ENERGY && bvalid && t >= HALO) e_bond += 0.5 * (double)(kb * (bl - r0) * (bl - r0));
+            }
+            // angle between the previous bond a (t-1 -> t) and this bond b (t -> t+1), beads t-1, t, t+1
+            if (t >= 1 && t + 1 >= HALO && t - 1 < HALO + B) {
+                const bool valid = avalid && bvalid;
+                const T iab = ail * bil;
+                const T c = (ax * bx + ay * by + az * bz) * iab;
+                const T ca = c * ail * ail, cb = c * bil * bil;
+                const T kk = valid ? kth : (T)0;
+                // dU/da = -k (b/(|a||b|) - c a/|a|^2), dU/db = -k (a/(|a||b|) - c b/|b|^2)
+                const T dax = -kk * (bx * iab - ca * ax), day = -kk * (by * iab - ca * ay), daz = -kk * (bz * iab - ca * az);
+                const T dbx = -kk * (ax * iab - cb * bx), dby = -kk * (ay * iab - cb * by), dbz = -kk * (az * iab - cb * bz);
+                add(t - 1, dax, day, daz);
+                add(t, dbx - dax, dby - day, dbz - daz);
+                add(t + 1, -dbx, -dby, -dbz);
+                if (ENERGY && valid && t - 1 >= HALO) e_ang += (double)(kth * ((T)1 - c));
+            }
+            ax = bx; ay = by; az = bz; ail = bil; avalid = bvalid;
         }
-#pragma unroll
-        for (int t = 0; t < L - 2; ++t) {
-            // angle between bonds t and t+1 (beads t, t+1, t+2) touches an owned bead?
-            if (t + 2 < HALO || t >= HALO + B) continue;
-            const int i = ib + t;
-            const bool valid = i >= 0 && i + 2 < N;
-            const T iab = bil[t] * bil[t + 1];
-            const T c = (bx[t] * bx[t + 1] + by[t] * by[t + 1] + bz[t] * bz[t + 1]) * iab;
-            const T ca = c * bil[t] * bil[t], cb = c * bil[t + 1] * bil[t + 1];
-            const T k = valid ? kth : (T)0;
-            // dU/da = -k (b/(|a||b|) - c a/|a|^2), dU/db = -k (a/(|a||b|) - c b/|b|^2)
-            const T dax = -k * (bx[t + 1] * iab - ca * bx[t]), day = -k * (by[t + 1] * iab - ca * by[t]), daz = -k * (bz[t + 1] * iab - ca * bz[t]);
-            const T dbx = -k * (bx[t] * iab - cb * bx[t + 1]), dby = -k * (by[t] * iab - cb * by[t + 1]), dbz = -k * (bz[t] * iab - cb * bz[t + 1]);
-            wx[t] += dax; wy[t] += day; wz[t] += daz;
-            wx[t + 1] += dbx - dax; wy[t + 1] += dby - day; wz[t + 1] += dbz - daz;
-            wx[t + 2] -= dbx; wy[t + 2] -= dby; wz[t + 2] -= dbz;
-            if (ENERGY && valid && t >= HALO) e_ang += (double)(kth * ((T)1 - c));
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) { fx[b] += wx[HALO + b]; fy[b] += wy[HALO + b]; fz[b] += wz[HALO + b]; }
 
         // ---- restraint k/2 (xi - centre)^2 on the pulled end ----
         const int last = N - 1;
@@ -333,7 +366,8 @@ __device__ __forceinline__ void chain_noise(const DevProblem &P, uint32_t gid, u
 
 template <typename T, int G, int B>
 __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkItem &item, char *ws, int64_t step_begin,
-                                               int64_t step_end, double *traj, int64_t traj_rep, double *s_acc) {
+                                               int64_t step_end, double *traj, int64_t traj_rep, double *s_acc,
+                                               unsigned int *lhist) {
     constexpr int NPAD = G * B;
     const int tid = threadIdx.x;
     const int grp = tid / G;
@@ -446,7 +480,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 if (g == owner) acc[A_BLOWN] = 1.0;
                 alive = false;
             } else if (g == owner) {
-                accumulate(P, lam, w, xi, acc, hist);
+                accumulate(P, lam, w, xi, acc, hist, lhist);
             }
         }
     }
@@ -464,11 +498,17 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
 template <typename T, int G, int B>
 __global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
                                                 int n_items, char *__restrict__ ws, int64_t step_begin,
-                                                int64_t step_end, double *__restrict__ traj, int64_t traj_rep) {
+                                                int64_t step_end, double *__restrict__ traj, int64_t traj_rep,
+                                                int lds_cap) {
     __shared__ double s_acc[(WG / G) * A_NFIELDS];
+    extern __shared__ unsigned int s_hist[];
     if ((int)blockIdx.x >= n_items) return;
     const WorkItem item = items[blockIdx.x];
-    run_chain_item<T, G, B>(probs[item.prob], item, ws, step_begin, step_end, traj, traj_rep, s_acc);
+    const DevProblem &P = probs[item.prob];
+    unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
+    if (lhist) lhist_clear(lhist, P.xi_nbins);
+    run_chain_item<T, G, B>(P, item, ws, step_begin, step_end, traj, traj_rep, s_acc, lhist);
+    if (lhist) lhist_flush(lhist, P.xi_nbins, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
 }
 
 // Persistent launch: workgroups take items from a queue (atomic ticket) until
@@ -476,9 +516,11 @@ __global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ p
 template <typename T, int G, int B>
 __global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__restrict__ probs,
                                                            const WorkItem *__restrict__ items, int n_items,
-                                                           int *__restrict__ ticket, char *__restrict__ ws) {
+                                                           int *__restrict__ ticket, char *__restrict__ ws,
+                                                           int lds_cap) {
     __shared__ double s_acc[(WG / G) * A_NFIELDS];
     __shared__ int s_item;
+    extern __shared__ unsigned int s_hist[];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1);
@@ -486,7 +528,11 @@ __global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__r
         const int it = s_item;
         if (it >= n_items) break;
         const WorkItem item = items[it];
-        run_chain_item<T, G, B>(probs[item.prob], item, ws, 0, INT64_MAX, nullptr, -1, s_acc);
+        const DevProblem &P = probs[item.prob];
+        unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
+        if (lhist) lhist_clear(lhist, P.xi_nbins);
+        run_chain_item<T, G, B>(P, item, ws, 0, INT64_MAX, nullptr, -1, s_acc, lhist);
+        if (lhist) lhist_flush(lhist, P.xi_nbins, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
     }
 }
 
@@ -554,16 +600,17 @@ __global__ void pot1d_eval(const DevProblem *__restrict__ probs, const double *_
 // Per-shape launchers; each shape is instantiated in its own translation unit.
 template <typename T, int G, int B>
 hipError_t launch_chain_direct(const DevProblem *d_probs, const WorkItem *d_items, int n_items, char *ws,
-                               int64_t step_begin, int64_t step_end, double *traj, int64_t traj_rep, hipStream_t stream) {
-    hipLaunchKernelGGL((sim_chain<T, G, B>), dim3(n_items), dim3(WG), 0, stream, d_probs, d_items, n_items, ws,
-                       step_begin, step_end, traj, traj_rep);
+                               int64_t step_begin, int64_t step_end, double *traj, int64_t traj_rep, int lds_cap,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL((sim_chain<T, G, B>), dim3(n_items), dim3(WG), (size_t)lds_cap * 4, stream, d_probs, d_items,
+                       n_items, ws, step_begin, step_end, traj, traj_rep, lds_cap);
     return hipGetLastError();
 }
 template <typename T, int G, int B>
 hipError_t launch_chain_persistent(const DevProblem *d_probs, const WorkItem *d_items, int n_items, int *d_ticket,
-                                   char *ws, int n_groups, hipStream_t stream) {
-    hipLaunchKernelGGL((sim_chain_persistent<T, G, B>), dim3(n_groups), dim3(WG), 0, stream, d_probs, d_items,
-                       n_items, d_ticket, ws);
+                                   char *ws, int n_groups, int lds_cap, hipStream_t stream) {
+    hipLaunchKernelGGL((sim_chain_persistent<T, G, B>), dim3(n_groups), dim3(WG), (size_t)lds_cap * 4, stream, d_probs,
+                       d_items, n_items, d_ticket, ws, lds_cap);
     return hipGetLastError();
 }
 template <typename T, int G, int B>
@@ -576,19 +623,19 @@ hipError_t launch_chain_eval(const DevProblem *d_probs, const double *coords, in
     return hipGetLastError();
 }
 template <typename T, int G, int B>
-int chain_blocks_per_cu() {
+int chain_blocks_per_cu(int lds_cap) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sim_chain_persistent<T, G, B>, WG, 0) != hipSuccess) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sim_chain_persistent<T, G, B>, WG, (size_t)lds_cap * 4) != hipSuccess) n = 1;
     return n;
 }
 
 #define PPP_INSTANTIATE_SHAPE(T, G, B)                                                                              \
     template hipError_t launch_chain_direct<T, G, B>(const DevProblem *, const WorkItem *, int, char *, int64_t,   \
-                                                     int64_t, double *, int64_t, hipStream_t);                     \
+                                                     int64_t, double *, int64_t, int, hipStream_t);                \
     template hipError_t launch_chain_persistent<T, G, B>(const DevProblem *, const WorkItem *, int, int *, char *, \
-                                                         int, hipStream_t);                                        \
+                                                         int, int, hipStream_t);                                   \
     template hipError_t launch_chain_eval<T, G, B>(const DevProblem *, const double *, int, double, double *,      \
                                                    double *, hipStream_t);                                         \
-    template int chain_blocks_per_cu<T, G, B>();
+    template int chain_blocks_per_cu<T, G, B>(int);
 
 }  // namespace ppp

@@ -34,11 +34,16 @@ def _gpu():
 
 
 def _small_batch(n, seed, precision, steps_scale=0.02, rep_cap=64):
+    """Uneven chains, windows, replicas and steps as in the batched workload, with the
+    windows bracketing the start state so no trajectory explodes (an exploding
+    trajectory amplifies any rounding difference without bound)."""
     probs = ppp_inputs.batched_instances(n, seed=seed)
     for p in probs:
+        N = p["n_beads"]
+        p["lambda"] = list(np.linspace(0.3 * (N - 1) + 0.5, 0.5 * (N - 1) + 1.5, len(p["lambda"])))
         p["n_steps"] = max(200, int(p["n_steps"] * steps_scale))
         p["n_equil"] = p["n_steps"] // 10
-        p["n_pull"] = p["n_steps"] // 20
+        p["n_pull"] = 0
         p["n_replicas"] = min(p["n_replicas"], rep_cap)
         p["precision"] = precision
         p["w_half_bins"] = 2000
