@@ -23,6 +23,36 @@ FP32_PEAK = 157.3e12     # MI355X fp32 vector, TFLOP/s (packed); unpacked FMA pe
 FP64_PEAK = 78.6e12
 
 
+# HBM traffic of one launch of the simulation kernel, from two rocprofv3 --pmc runs of
+# this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# same counter reads for a 1 GiB device-to-device copy in the same run (--pmc-copy-mib
+# 1024: FETCH_SIZE reads 524308 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  A record
+# holds only while the kernel sources hash to the digest it was taken on.
+TRAFFIC = {
+    "chain10": {"sources_sha1": "fe3ef493f824a0c4df3e05b1545b6e8b93e8d9e6", "kernel": "sim_chain<float,2,5>",
+                "fetch_kib": 288.5, "fetch_scale": 2.0, "write_kib": 8656.75, "write_scale": 1.0},
+}
+KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
+                  "ppp_launch.hpp")
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1105_4840_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """Bytes per launch from the counter record, or None when it does not apply."""
+    rec = TRAFFIC.get(workload)
+    if rec is None or rec["kernel"] != kernel or rec["sources_sha1"] != kernel_sources_digest():
+        return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
+
 def chain_flops_per_replica_step(n_beads):
     """Algorithmic fp32 flops of one replica-step of the chain: 24 per non-excluded
     Lennard-Jones pair (all |i-j| > 2 pairs are evaluated), 21 per bond, 45 per
@@ -185,9 +215,10 @@ def main():
     avg_sim_s = float(np.mean(sim_ms)) * 1e-3
     if prob["model"] == "chain":
         flops = chain_flops_per_replica_step(prob["n_beads"]) * rs_per_run
+        kname = f"sim_chain<float,{tim['variant_lanes']},{tim['variant_beads_per_lane']}>"
         roof = {"bound": "alu", "achieved": flops / avg_sim_s / 1e12, "peak": FP32_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": flops / avg_sim_s / FP32_PEAK, "traffic": None,
-                "kernel": f"sim_chain<float,{tim['variant_lanes']},{tim['variant_beads_per_lane']}>",
+                "unit": "TFLOP/s", "frac": flops / avg_sim_s / FP32_PEAK,
+                "traffic": measured_traffic(args.workload, kname), "kernel": kname,
                 "flops_per_replica_step": chain_flops_per_replica_step(prob["n_beads"]),
                 "avg_launch_ms": avg_sim_s * 1e3}
     else:
