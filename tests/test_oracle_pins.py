@@ -358,3 +358,72 @@ def test_appc_bounds_against_product_form():
     r = estimators.estimate(p, xi, kept, with_appc=False)
     tol = np.cumsum(np.concatenate([[0], p["k"] * np.abs(np.diff(p["lambda"])) * p["xi_bin"] / 2]))
     assert np.all(np.abs(prod - r["dF_je"]) <= tol + 1e-9)
+
+
+# --------------------------------------------------------------------------- statistics of the estimators
+
+
+def _synthetic(samples_per_window, lam, k, kT, blocks, xi_bin=1e-3, xi_min=-10.0):
+    """Problem and sample arrays for the estimators from given per-window samples
+    (one sample per replica, so a jackknife block is a set of replicas)."""
+    R = len(samples_per_window[0])
+    xi = np.concatenate([np.asarray(s, dtype=np.float64) for s in samples_per_window])[:, None]
+    kept = np.ones(len(xi), dtype=np.int64)
+    p = {"lambda": list(lam), "k": k, "kT": kT, "n_replicas": R, "n_blocks": blocks,
+         "xi_min": xi_min, "xi_bin": xi_bin, "xi_nbins": int(round(-2 * xi_min / xi_bin)), "w_half_bins": 0}
+    return p, xi, kept
+
+
+def test_jackknife_se_of_a_mean_is_the_standard_error():
+    """dF_fluct of the second window is linear in the first window's mean, and the
+    delete-one jackknife error of a sample mean is exactly s / sqrt(n)."""
+    rng = np.random.default_rng(3)
+    R = 50
+    x1 = rng.normal(0.7, 0.3, R); x2 = rng.normal(1.1, 0.3, R)
+    k, dl = 7.0, 0.5
+    p, xi, kept = _synthetic([x1, x2], [0.5, 0.5 + dl], k, 1.0, blocks=R)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    assert abs(r["dF_fluct"][1] - k * dl * (0.5 - x1.mean())) < 1e-12
+    assert abs(r["dF_fluct_se"][1] - k * dl * np.std(x1, ddof=1) / np.sqrt(R)) < 1e-12
+
+
+def test_gaussian_samples_give_exact_forward_and_reverse_profiles():
+    """Exact restrained-harmonic samples (x ~ N(k lam/(kappa+k), kT/(kappa+k))):
+    forward JE, reverse JE and Eq. 13 converge to kappa k (lam_j^2 - lam_1^2) / (2 (kappa+k));
+    the Kish fraction of a Gaussian exponent of variance v is exp(-v); the overlap of two
+    equal-width Gaussians is 2 Phi(-|dmu| / (2 sigma))."""
+    from scipy.stats import norm
+    kappa, k, kT = 4.0, 20.0, 0.8
+    lam = np.array([-0.3, -0.15, 0.0, 0.12, 0.3])
+    Fc, mu, var = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    rng = np.random.default_rng(11)
+    R = 100000
+    smp = [rng.normal(m, np.sqrt(v), R) for m, v in zip(mu, var)]
+    p, xi, kept = _synthetic(smp, lam, k, kT, blocks=16, xi_bin=0.01)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    exact = Fc - Fc[0]
+    for key in ("dF_je", "dF_gauss"):
+        assert np.all(np.abs(r[key] - exact) <= 5 * r[key + "_se"] + 1e-12), (key, r[key] - exact)
+    # reverse JE (no jackknife): its spread is that of the forward estimate in this symmetric case
+    assert np.all(np.abs(r["dF_rev"] - exact) <= 5 * r["dF_je_se"] + 1e-3), r["dF_rev"] - exact
+    beta = 1.0 / kT
+    v = (beta * k * np.diff(lam)) ** 2 * var[:-1]
+    assert np.allclose(r["kish_frac"][:-1], np.exp(-v), rtol=0.02), (r["kish_frac"], np.exp(-v))
+    ovl = 2 * norm.cdf(-np.abs(np.diff(mu)) / (2 * np.sqrt(var[:-1])))
+    assert np.allclose(r["overlap_ovl"], ovl, atol=0.01), (r["overlap_ovl"], ovl)
+    assert np.allclose(r["gamma2"], k / (kappa + k), rtol=0.01)
+
+
+def test_reach_criterion_hand_case():
+    """Reach = end of the window's samples in the pulling direction minus their mean."""
+    lam = [0.0, 1.0, 3.0]
+    smp = [[-1.0, 0.0, 1.0, 2.0], [0.0, 1.0, 1.0, 2.0], [2.0, 3.0, 3.0, 4.0]]
+    p, xi, kept = _synthetic(smp, lam, 10.0, 1.0, blocks=2)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    assert np.allclose(r["reach"], [2.0 - 0.5, 2.0 - 1.0])
+    assert np.allclose(r["dlambda_over_reach"], [1.0 / 1.5, 2.0 / 1.0])
+    assert list(r["criterion_ok"]) == [True, False]
+    # pulling towards smaller lambda measures the reach on the other side
+    p2, xi2, kept2 = _synthetic(smp[::-1], lam[::-1], 10.0, 1.0, blocks=2)
+    r2 = estimators.estimate(p2, xi2, kept2, with_appc=False)
+    assert np.allclose(r2["reach"], [3.0 - 2.0, 1.0 - 0.0])
