@@ -70,6 +70,9 @@ WORKLOADS = {
                 "4096 replicas/window, 23251 steps (2e9 replica-steps)"),
     "chain256": ("config_chain256", "256-bead chain, same force field, all LJ pairs, k=20, 41 windows in [10, 200], "
                  "4096 replicas/window, 200000 steps"),
+    "batch": ("batched_instances", "64 independent chains in one persistent, graph-captured launch: lengths "
+              "U{8..128}, 11-41 windows, 64-1024 replicas/window, 5e3-1e5 steps (log-uniform), same force field, "
+              "k=20, fp32 forces/fp64 work"),
     "1d": ("config_1d", "1-D double well U=5(x^2-1)^2, k=50, 21 windows in [-1.5, 1.5], 256 replicas/window, "
            "20000 overdamped LM steps dt=1e-3, fp64"),
 }
@@ -139,6 +142,68 @@ def placement_study(args):
                       "rows": rows}), flush=True)
 
 
+def batch_bench(args, desc):
+    """The uneven batch: every problem in one graph launch (persistent kernels per
+    kernel shape on side streams, then reductions, estimators and App. C)."""
+    import numpy as np
+    import torch
+    import paper_1105_4840_amd as ppp
+    import ppp_inputs
+    probs = ppp_inputs.batched_instances()
+    table = None
+    if args.tune:
+        import tempfile
+        table = os.path.join(tempfile.mkdtemp(), "tune.txt")
+        tws = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        st = ppp.lib().ppp_autotune(table.encode(), ppp._ptr(tws), tws.numel(), ppp._stream())
+        if st != ppp.PPP_OK:
+            raise RuntimeError(f"ppp_autotune: {ppp.lib().ppp_status_string(st)}")
+        del tws
+        print("# autotune done", file=sys.stderr, flush=True)
+    h = ppp.ppp_batch_create(probs, table)
+    ws = ppp.workspace(h)
+    rs_per_run = sum(len(p["lambda"]) * p["n_replicas"] * p["n_steps"] for p in probs)
+    flops = sum(len(p["lambda"]) * p["n_replicas"] * p["n_steps"] * chain_flops_per_replica_step(p["n_beads"])
+                for p in probs)
+    for i in range(args.warmup):
+        ppp.ppp_run(h, ws)
+        torch.cuda.synchronize()
+        print(f"# warmup run {i + 1} done", file=sys.stderr, flush=True)
+    graph_ms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ppp.ppp_run(h, ws)
+        torch.cuda.synchronize()
+        graph_ms.append(ppp.ppp_get_timings(h)["sim_ms"])
+        print(f"# run {i + 1} done: {graph_ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    frozen = 0; worst = 0.0
+    for i, p in enumerate(probs):
+        r = ppp.ppp_batch_get_result(h, p, i)
+        frozen += int(r["n_blown_up"].sum())
+        worst = max(worst, float(np.max(r["n_blown_up"] / p["n_replicas"])))
+    tim = ppp.ppp_get_timings(h)
+    ppp.ppp_destroy(h)
+    avg_s = float(np.mean(graph_ms)) * 1e-3
+    out = {
+        "metric": METRIC, "value": rs_per_run * args.steps / el, "unit": "replica-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch", "description": desc, "problems": len(probs),
+                   "replica_steps_per_step": rs_per_run, "tune_table": bool(args.tune), "parallelism": "1 GPU"},
+        "graph_replica_steps_per_s": rs_per_run / avg_s,
+        "accuracy": {"frozen_replicas": frozen, "worst_window_frozen_fraction": worst},
+        # the graph holds one persistent kernel per kernel shape, run concurrently; the
+        # achieved rate is the whole graph's (reductions included, < 1% of it)
+        "roofline": {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": FP32_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": flops / avg_s / FP32_PEAK, "traffic": None,
+                     "kernel": "sim_chain_persistent<float,G,B> (all shapes, one graph)",
+                     "flops_per_run": flops, "avg_launch_ms": avg_s * 1e3},
+        "timings_ms": {"graph": tim["sim_ms"], "total": tim["total_ms"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +217,11 @@ def main():
                     help="dF error at equal budget, uniform vs learned windows (32-bead chain)")
     ap.add_argument("--ref-steps", type=int, default=40000)
     ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
+    ap.add_argument("--profile-launches", type=int, default=0,
+                    help="with --chunk: stop after this many advances and print no bench line "
+                         "(for counter collection on one launch of a long workload)")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch workload: run the autotuner first and use its table")
     ap.add_argument("--pmc-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -170,9 +240,12 @@ def main():
         placement_study(args)
         return
     fn, desc = WORKLOADS[args.workload]
-    prob = getattr(ppp_inputs, fn)()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "batch":
+        batch_bench(args, desc)
+        return
+    prob = getattr(ppp_inputs, fn)()
     h = ppp.ppp_create(prob)
     ws = ppp.workspace(h)
     rs_per_run = len(prob["lambda"]) * prob["n_replicas"] * prob["n_steps"]
@@ -196,6 +269,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile_launches > 0:
+        if args.chunk <= 0:
+            raise SystemExit("--profile-launches needs --chunk")
+        ppp.ppp_begin(h, ws, stream)
+        for i in range(args.profile_launches):
+            t0 = time.perf_counter()
+            ppp.ppp_advance(h, args.chunk, stream)
+            torch.cuda.synchronize()
+            print(f"# profiled advance {i + 1}: {(time.perf_counter() - t0) * 1e3:.1f} ms wall", file=sys.stderr,
+                  flush=True)
+        ppp.ppp_destroy(h)
+        return
     for _ in range(args.warmup):
         one_run()
     torch.cuda.synchronize()

@@ -244,6 +244,39 @@ def test_fp32_chain_statistics_match_oracle():
         assert abs(res[key][-1] - ref[key][-1]) < 3.5 * se, (key, res[key][-1], ref[key][-1], se)
 
 
+FP32_SLICES = [
+    # (name, problem, estimators asserted): the workloads' own step counts, fewer replicas
+    ("chain10", lambda: ppp_inputs.config_chain10(n_replicas=64), ("dF_je", "dF_fluct", "dF_gauss", "dF_com")),
+    # uniform windows 5.7 sigma apart: JE rests on rare samples there, so only its
+    # error is stated; the moment-based estimators are asserted
+    ("chain32", lambda: ppp_inputs.config_chain32(n_replicas=16), ("dF_fluct", "dF_gauss")),
+]
+
+
+@pytest.mark.parametrize("case", FP32_SLICES, ids=[c[0] for c in FP32_SLICES])
+def test_fp32_error_vs_fp64_oracle(case):
+    """Precision split: fp32 forces and integration with fp64 work accumulation
+    against the all-fp64 oracle on the same inputs and noise streams; the error
+    of every dF at the last window is printed and checked against 3.5 combined
+    jackknife standard errors."""
+    name, make, asserted = case
+    _say(f"case fp32 vs fp64 oracle {name}")
+    prob = make()
+    prob["n_blocks"] = 16
+    res, _ = ppp.run(prob)
+    p64 = dict(prob, precision="fp64")
+    xi, kept, _ = oracle.run(p64)
+    ref = estimators.estimate(p64, xi, kept, with_appc=False)
+    line = []
+    for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com"):
+        err = res[key][-1] - ref[key][-1]
+        se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
+        line.append(f"{key} gpu {res[key][-1]:.4f} oracle {ref[key][-1]:.4f} err {err:+.4f} (combined se {se:.4f})")
+        if key in asserted:
+            assert abs(err) < 3.5 * se, line[-1]
+    _say(f"fp32 error {name}: " + "; ".join(line))
+
+
 def _shapes():
     from paper_1105_4840_amd import build
     return build.shapes()
