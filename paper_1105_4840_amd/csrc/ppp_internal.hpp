@@ -75,10 +75,19 @@ struct DevProblem {
     int64_t off_omega;      // double [s][2M+1]
 };
 
+// n_reps consecutive replicas of one problem, starting at replica rep_begin of
+// window `window`.  Replicas are numbered gid = window * R + replica, so an item
+// of a chain problem may run on into the following windows (the kernels take
+// each replica's window from its own gid).
 struct WorkItem {
     int32_t prob, window, rep_begin, n_reps;
 };
 
 constexpr int WG = 256;  // threads per workgroup of the simulation kernels
+
+// Chain kernels give each replica G consecutive lanes of one wavefront; a
+// wavefront holds 64 / G whole groups and its last 64 mod G lanes stay idle.
+constexpr int groups_per_wave(int G) { return 64 / G; }
+constexpr int chain_reps_per_wg(int G) { return (WG / 64) * groups_per_wave(G); }
 
 }  // namespace ppp

@@ -36,6 +36,7 @@ struct ProblemHost {
     DevProblem dev{};
     int G = 1, B = 1;
     int first_item = 0, n_items = 0;
+    int item_windows = 1;        // most windows one work item's replicas fall in
     int64_t region_begin = 0, region_end = 0;   // byte range of this problem in the workspace
 };
 
@@ -159,10 +160,14 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
 // Kernel shape (lanes per replica G, beads per lane B) for a chain length.
 void default_shape(int N, int precision, int &G, int &B) {
     // measured on MI355X: short chains want a few lanes per replica to fill the
-    // chip, long chains more beads per lane for fewer rotation rounds; fp64 (twice
-    // the registers) keeps two beads per lane so that nothing spills
+    // chip (21504 ten-bead replicas: 5 lanes each give 1792 wavefronts for the
+    // 1024 SIMDs, 2 lanes only 672), long chains more beads per lane for fewer
+    // rotation rounds; fp64 (twice the registers) keeps two beads per lane so
+    // that nothing spills
     if (precision == PPP_FP64) {
         if (N <= 4) { G = 1; B = 4; }
+        else if (N <= 10) { G = 5; B = 2; }
+        else if (N <= 12) { G = 3; B = 4; }
         else if (N <= 16) { G = 8; B = 2; }
         else if (N <= 32) { G = 16; B = 2; }
         else if (N <= 64) { G = 32; B = 2; }
@@ -172,7 +177,8 @@ void default_shape(int N, int precision, int &G, int &B) {
     }
     if (N <= 4) { G = 1; B = 4; }
     else if (N <= 8) { G = 1; B = 8; }
-    else if (N <= 10) { G = 2; B = 5; }
+    else if (N <= 10) { G = 5; B = 2; }
+    else if (N <= 12) { G = 3; B = 4; }
     else if (N <= 16) { G = 4; B = 4; }
     else if (N <= 32) { G = 16; B = 2; }
     else if (N <= 64) { G = 16; B = 4; }
@@ -303,14 +309,32 @@ int64_t layout_problem(ProblemHost &ph, int64_t at) {
     return at;
 }
 
-int reps_per_item(const ProblemHost &ph) { return ph.dev.model == PPP_MODEL_CHAIN ? WG / ph.G : WG; }
+int reps_per_item(const ProblemHost &ph) { return ph.dev.model == PPP_MODEL_CHAIN ? chain_reps_per_wg(ph.G) : WG; }
 
-void make_items(ProblemHost &ph, int prob_index, std::vector<WorkItem> &items) {
+// Work items of one problem.  Per window (every item inside one window), or,
+// for chain problems whose windows do not split into whole items, as runs of
+// consecutive replicas that may cross into the next window (no workgroup is
+// left part empty at a window's end), provided the workgroup histogram of all
+// windows one item touches still fits in LDS.
+void make_items(ProblemHost &ph, int prob_index, std::vector<WorkItem> &items, bool allow_span) {
     const int per = reps_per_item(ph);
+    const int64_t R = ph.dev.n_replicas, total = (int64_t)ph.dev.n_windows * R;
     ph.first_item = (int)items.size();
-    for (int w = 0; w < ph.dev.n_windows; ++w)
-        for (int r = 0; r < ph.dev.n_replicas; r += per)
-            items.push_back(WorkItem{prob_index, w, r, std::min(per, ph.dev.n_replicas - r)});
+    ph.item_windows = 1;
+    const int64_t span_windows = (per - 1) / R + 2;   // a run of `per` replicas touches at most this many
+    const bool span = allow_span && ph.dev.model == PPP_MODEL_CHAIN && R % per != 0 &&
+                      span_windows * ph.dev.xi_nbins <= kLdsHistCap;
+    if (span) {
+        for (int64_t g = 0; g < total; g += per) {
+            const int n = (int)std::min<int64_t>(per, total - g);
+            items.push_back(WorkItem{prob_index, (int)(g / R), (int)(g % R), n});
+            ph.item_windows = std::max(ph.item_windows, (int)((g + n - 1) / R - g / R + 1));
+        }
+    } else {
+        for (int w = 0; w < ph.dev.n_windows; ++w)
+            for (int r = 0; r < ph.dev.n_replicas; r += per)
+                items.push_back(WorkItem{prob_index, w, r, std::min(per, ph.dev.n_replicas - r)});
+    }
     ph.n_items = (int)items.size() - ph.first_item;
 }
 
@@ -364,7 +388,8 @@ ppp_status ensure_events(ppp_handle *h) {
 
 ppp_status launch_items(ppp_handle *h, const ProblemHost &ph, int64_t b, int64_t e, hipStream_t st, double *traj,
                         int64_t traj_rep, int first, int count) {
-    const int cap = ph.dev.xi_nbins <= kLdsHistCap ? ph.dev.xi_nbins : 0;
+    const int64_t nk = (int64_t)ph.item_windows * ph.dev.xi_nbins;
+    const int cap = nk <= kLdsHistCap ? (int)nk : 0;
     HIPCHK(h, launch_sim(d_probs(h), d_items(h) + first, count, h->ws, b, e, ph.dev.model, ph.dev.precision, ph.G,
                          ph.B, traj, traj_rep, cap, st));
     return PPP_OK;
@@ -531,7 +556,7 @@ ppp_status ppp_create(const ppp_problem *p, ppp_handle **out) {
     // an optional shape table (written by ppp_autotune) named by PPP_TUNE_TABLE
     ppp_status s = build_problem(p, h->probs[0], read_tune_table(std::getenv("PPP_TUNE_TABLE")), msg);
     if (s != PPP_OK) { g_create_err = msg; delete h; return s; }
-    make_items(h->probs[0], 0, h->items);
+    make_items(h->probs[0], 0, h->items, true);
     finish_layout(h);
     *out = h;
     return PPP_OK;
@@ -567,7 +592,7 @@ ppp_status ppp_batch_create(const ppp_problem *ps, int32_t n, const char *tune_t
             ProblemHost &ph = h->probs[i];
             if (ph.dev.precision != k.prec || ph.G != k.G || ph.B != k.B) continue;
             std::vector<WorkItem> tmp;
-            make_items(ph, i, tmp);
+            make_items(ph, i, tmp, false);
             const double npair = 0.5 * (double)ph.dev.n_beads * ph.dev.n_beads + 20.0 * ph.dev.n_beads;
             for (auto &it : tmp) its.push_back({npair * it.n_reps * (double)ph.dev.n_steps, it});
         }
@@ -828,9 +853,14 @@ ppp_status ppp_trajectory(ppp_handle *h, void *ws, size_t bytes, int32_t window,
     h->ws = static_cast<char *>(ws);
     if ((s = upload(h, st)) != PPP_OK) return s;
     HIPCHK(h, launch_init(d_probs(h), 1, h->ws, h->max_windows, h->max_k, h->max_m, reinterpret_cast<int *>(h->ws + h->off_tickets), 64, st));
-    const int per = reps_per_item(ph);
-    const int item = ph.first_item + window * ((ph.dev.n_replicas + per - 1) / per) + replica / per;
     const int64_t gid = (int64_t)window * ph.dev.n_replicas + replica;
+    int item = -1;
+    for (int i = ph.first_item; i < ph.first_item + ph.n_items && item < 0; ++i) {
+        const WorkItem &it = h->items[i];
+        const int64_t g0 = (int64_t)it.window * ph.dev.n_replicas + it.rep_begin;
+        if (gid >= g0 && gid < g0 + it.n_reps) item = i;
+    }
+    if (item < 0) return fail(h, PPP_E_INVALID_ARG, "replica not in any work item");
     if ((s = launch_items(h, ph, 0, n_steps, st, d_out, gid, item, 1)) != PPP_OK) return s;
     h->begun = false; h->finalized = false;
     return PPP_OK;
@@ -882,7 +912,7 @@ ppp_status ppp_autotune(const char *path, void *ws, size_t bytes, void *stream) 
                 std::string msg;
                 std::vector<TuneEntry> force{TuneEntry{N, prec, G, B}};
                 if (build_problem(&p, h->probs[0], force, msg) != PPP_OK || h->probs[0].G != G || h->probs[0].B != B) { delete h; continue; }
-                make_items(h->probs[0], 0, h->items);
+                make_items(h->probs[0], 0, h->items, true);
                 finish_layout(h);
                 if (h->ws_bytes > (int64_t)bytes) { delete h; continue; }
                 ppp_status s2 = do_begin(h, ws, bytes, st);

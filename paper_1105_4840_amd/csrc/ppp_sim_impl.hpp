@@ -8,12 +8,14 @@
 //
 // Two kernels:
 //   * sim_1d: one lane per replica, overdamped dynamics of one coordinate.
-//   * sim_chain<T, G, B>: G consecutive lanes per replica (G in {1, 4, 16, 64}),
-//     B beads per lane in registers (lane g owns beads gB .. gB+B-1).  The
+//   * sim_chain<T, G, B>: G consecutive lanes of a wavefront per replica (any G
+//     up to 64; 64 / G groups per wavefront, the remaining lanes idle), B beads
+//     per lane in registers (lane g owns beads gB .. gB+B-1).  The
 //     Lennard-Jones sum uses each unique pair once (Newton's third law): the
 //     j-beads rotate one lane per round through the group together with an
 //     accumulator of their reaction forces, which finally is pushed back to
-//     the owning lane.  Bonded terms read a two-bead halo from the
+//     the owning lane (for even G the last round, which meets the opposite
+//     lane, is done from both sides instead).  Bonded terms read a two-bead halo from the
 //     neighbouring lanes.  Nothing leaves registers inside the step loop
 //     except the per-sample histogram increment (one u64 atomic).
 #pragma once
@@ -34,8 +36,8 @@ __device__ __forceinline__ bool sample_now(const DevProblem &P, int64_t n) {
 }
 
 // Folds one sample xi of window w into the replica's accumulator.  The
-// histogram count goes to the workgroup's LDS copy (lhist, all replicas of a
-// work item share one window) when there is one, else straight to memory.
+// histogram count goes to the workgroup's LDS copy of window w's histogram
+// (lhist) when there is one, else straight to memory.
 __device__ __forceinline__ void accumulate(const DevProblem &P, const double *lam, int w, double xi,
                                            double *acc, unsigned long long *hist, unsigned int *lhist) {
     const int s = P.n_windows;
@@ -78,6 +80,15 @@ __device__ __forceinline__ void lhist_flush(unsigned int *lhist, int K, unsigned
         if (c) atomicAdd(dst + b, (unsigned long long)c);
     }
     __syncthreads();
+}
+
+// Bins of the workgroup histogram of an item: K for every window its replicas
+// fall in (INT32_MAX when that would not fit an int).
+__device__ __forceinline__ int item_hist_bins(const DevProblem &P, const WorkItem &item) {
+    const int64_t last = (int64_t)item.window * P.n_replicas + item.rep_begin + item.n_reps - 1;
+    const int64_t nw = last / P.n_replicas - item.window + 1;
+    const int64_t nk = nw * (int64_t)P.xi_nbins;
+    return nk < (int64_t)INT32_MAX ? (int)nk : INT32_MAX;
 }
 
 template <typename T> __device__ __forceinline__ T *state_ptr(char *ws, const DevProblem &P) {
@@ -206,13 +217,17 @@ struct ChainForce {
         }
     }
 
-    // Forces on the owned beads at restraint centre `centre`.  lane g of group base `gbase`.
+    // Forces on the owned beads at restraint centre `centre`.  lane g of group base `gbase`;
+    // an idle lane (beyond the wavefront's last whole group: gbase + G > 64) only
+    // exchanges data with itself.
     // e[0..3] = bond, angle, lj, restraint energy contributions of this lane (ENERGY only).
     __device__ __forceinline__ static void compute(const DevProblem &P, int g, int gbase, T centre,
                                                    const T (&px)[B], const T (&py)[B], const T (&pz)[B],
                                                    T (&fx)[B], T (&fy)[B], T (&fz)[B], double *e) {
         const int N = P.n_beads;
         const int i0 = g * B;
+        const bool solo = gbase + G > 64;
+        const int me = lane_id();
         const T lA = (T)P.lj_A, lB = (T)P.lj_B, rc2 = (T)P.rc2;
         double e_lj = 0.0, e_bond = 0.0, e_ang = 0.0, e_res = 0.0;
 #pragma unroll
@@ -242,13 +257,15 @@ struct ChainForce {
             for (int b = 0; b < B; ++b) { qx[b] = px[b]; qy[b] = py[b]; qz[b] = pz[b]; gx[b] = 0; gy[b] = 0; gz[b] = 0; }
             int jo = g;                 // lane that owns the beads now held in q
             int jo_n3 = g;
-            const int src = gbase + ((g + G - 1) % G);
+            const int src = solo ? me : gbase + ((g + G - 1) % G);
 #pragma unroll 1
             for (int r = 1; r <= G / 2; ++r) {
 #pragma unroll
                 for (int b = 0; b < B; ++b) { qx[b] = pull_f(src, qx[b]); qy[b] = pull_f(src, qy[b]); qz[b] = pull_f(src, qz[b]); }
                 jo = pull_i(src, jo);
-                const bool n3 = r < G / 2;
+                // rounds that meet every lane pair once keep the reactions; the round
+                // meeting the opposite lane of an even group is done from both sides
+                const bool n3 = 2 * r < G;
                 if (n3 && r > 1) {
 #pragma unroll
                     for (int b = 0; b < B; ++b) { gx[b] = pull_f(src, gx[b]); gy[b] = pull_f(src, gy[b]); gz[b] = pull_f(src, gz[b]); }
@@ -270,7 +287,7 @@ struct ChainForce {
             }
             if constexpr (G > 2) {
                 // reaction forces go back to the lane owning those beads
-                const int dst = gbase + jo_n3;
+                const int dst = solo ? me : gbase + jo_n3;
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     fx[b] += push_f(dst, gx[b]); fy[b] += push_f(dst, gy[b]); fz[b] += push_f(dst, gz[b]);
@@ -284,8 +301,8 @@ struct ChainForce {
         // the one or two terms it shares with a neighbour lane).
         T hx[2 * HALO + 1], hy[2 * HALO + 1], hz[2 * HALO + 1];   // halo beads (prev lane's last two, next lane's first two)
         if constexpr (G > 1) {
-            const int prev = gbase + (g > 0 ? g - 1 : 0);
-            const int next = gbase + (g + 1 < G ? g + 1 : G - 1);
+            const int prev = solo ? me : gbase + (g > 0 ? g - 1 : 0);
+            const int next = solo ? me : gbase + (g + 1 < G ? g + 1 : G - 1);
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 hx[hh] = pull_f(prev, px[B - 2 + hh]); hy[hh] = pull_f(prev, py[B - 2 + hh]); hz[hh] = pull_f(prev, pz[B - 2 + hh]);
@@ -369,16 +386,20 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                                                int64_t step_end, double *traj, int64_t traj_rep, double *s_acc,
                                                unsigned int *lhist) {
     constexpr int NPAD = G * B;
-    const int tid = threadIdx.x;
-    const int grp = tid / G;
-    const int g = tid % G;
-    const int gbase = lane_id() - g;
-    const int rep = item.rep_begin + grp;
-    const bool active = grp < item.n_reps;
+    constexpr int GPW = groups_per_wave(G);
+    const int lane = lane_id();
+    const bool lane_used = lane < GPW * G;
+    const int grp = (int)(threadIdx.x >> 6) * GPW + (lane_used ? lane / G : 0);
+    const int g = lane_used ? lane % G : 0;
+    const int gbase = lane_used ? lane - g : lane;
+    const bool active = lane_used && grp < item.n_reps;
     const int N = P.n_beads;
-    const int w = item.window;
-    const int64_t gi = (int64_t)w * P.n_replicas + (active ? rep : item.rep_begin);
+    const int64_t gfirst = (int64_t)item.window * P.n_replicas + item.rep_begin;
+    const int64_t gi = gfirst + (active ? grp : 0);
+    const int w = (int)(gi / P.n_replicas);      // this replica's window
     const uint32_t gid = (uint32_t)gi;
+    // the workgroup's histogram holds the windows item.window, item.window + 1, ...
+    unsigned int *lhist_w = lhist ? lhist + (int64_t)(w - item.window) * P.xi_nbins : nullptr;
     const double *lam = reinterpret_cast<const double *>(ws + P.off_lambda);
     const double *x0 = reinterpret_cast<const double *>(ws + P.off_init);
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
@@ -405,14 +426,14 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 vx[b] = (T)P.sd_v * z[0]; vy[b] = (T)P.sd_v * z[1]; vz[b] = (T)P.sd_v * z[2];
             }
         }
-        if (g == owner) acc_empty(acc);
+        if (lane_used && g == owner) acc_empty(acc);
     } else {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             px[b] = st[0 * NPAD + i0 + b]; py[b] = st[1 * NPAD + i0 + b]; pz[b] = st[2 * NPAD + i0 + b];
             vx[b] = st[3 * NPAD + i0 + b]; vy[b] = st[4 * NPAD + i0 + b]; vz[b] = st[5 * NPAD + i0 + b];
         }
-        if (g == owner) for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
+        if (lane_used && g == owner) for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
     }
     const bool record = traj != nullptr && gi == traj_rep && active;
     if (record && step_begin == 0) {
@@ -480,7 +501,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 if (g == owner) acc[A_BLOWN] = 1.0;
                 alive = false;
             } else if (g == owner) {
-                accumulate(P, lam, w, xi, acc, hist, lhist);
+                accumulate(P, lam, w, xi, acc, hist, lhist_w);
             }
         }
     }
@@ -500,15 +521,16 @@ __global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ p
                                                 int n_items, char *__restrict__ ws, int64_t step_begin,
                                                 int64_t step_end, double *__restrict__ traj, int64_t traj_rep,
                                                 int lds_cap) {
-    __shared__ double s_acc[(WG / G) * A_NFIELDS];
+    __shared__ double s_acc[chain_reps_per_wg(G) * A_NFIELDS];
     extern __shared__ unsigned int s_hist[];
     if ((int)blockIdx.x >= n_items) return;
     const WorkItem item = items[blockIdx.x];
     const DevProblem &P = probs[item.prob];
-    unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
-    if (lhist) lhist_clear(lhist, P.xi_nbins);
+    const int nk = item_hist_bins(P, item);
+    unsigned int *lhist = nk <= lds_cap ? s_hist : nullptr;
+    if (lhist) lhist_clear(lhist, nk);
     run_chain_item<T, G, B>(P, item, ws, step_begin, step_end, traj, traj_rep, s_acc, lhist);
-    if (lhist) lhist_flush(lhist, P.xi_nbins, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
+    if (lhist) lhist_flush(lhist, nk, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
 }
 
 // Persistent launch: workgroups take items from a queue (atomic ticket) until
@@ -518,7 +540,7 @@ __global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__r
                                                            const WorkItem *__restrict__ items, int n_items,
                                                            int *__restrict__ ticket, char *__restrict__ ws,
                                                            int lds_cap) {
-    __shared__ double s_acc[(WG / G) * A_NFIELDS];
+    __shared__ double s_acc[chain_reps_per_wg(G) * A_NFIELDS];
     __shared__ int s_item;
     extern __shared__ unsigned int s_hist[];
     for (;;) {
@@ -529,10 +551,11 @@ __global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__r
         if (it >= n_items) break;
         const WorkItem item = items[it];
         const DevProblem &P = probs[item.prob];
-        unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
-        if (lhist) lhist_clear(lhist, P.xi_nbins);
+        const int nk = item_hist_bins(P, item);
+        unsigned int *lhist = nk <= lds_cap ? s_hist : nullptr;
+        if (lhist) lhist_clear(lhist, nk);
         run_chain_item<T, G, B>(P, item, ws, 0, INT64_MAX, nullptr, -1, s_acc, lhist);
-        if (lhist) lhist_flush(lhist, P.xi_nbins, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
+        if (lhist) lhist_flush(lhist, nk, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
     }
 }
 
@@ -542,11 +565,14 @@ __global__ __launch_bounds__(WG) void chain_eval(const DevProblem *__restrict__ 
                                                  int n_rep, double centre, double *__restrict__ forces,
                                                  double *__restrict__ energy) {
     const DevProblem &P = probs[0];
-    const int tid = threadIdx.x;
-    const int grp = tid / G, g = tid % G;
-    const int gbase = lane_id() - g;
-    const int c = blockIdx.x * (WG / G) + grp;
-    const bool active = c < n_rep;
+    constexpr int GPW = groups_per_wave(G);
+    const int lane = lane_id();
+    const bool lane_used = lane < GPW * G;
+    const int grp = (int)(threadIdx.x >> 6) * GPW + (lane_used ? lane / G : 0);
+    const int g = lane_used ? lane % G : 0;
+    const int gbase = lane_used ? lane - g : lane;
+    const int c = blockIdx.x * chain_reps_per_wg(G) + grp;
+    const bool active = lane_used && c < n_rep;
     const int cc = active ? c : 0;
     const int N = P.n_beads;
     const int i0 = g * B;
@@ -563,7 +589,7 @@ __global__ __launch_bounds__(WG) void chain_eval(const DevProblem *__restrict__ 
     double tot[4];
     for (int q = 0; q < 4; ++q) {
         double s = 0.0;
-        for (int l = 0; l < G; ++l) s += pull_f(gbase + l, e[q]);
+        for (int l = 0; l < G; ++l) s += pull_f(lane_used ? gbase + l : lane, e[q]);
         tot[q] = s;
     }
     if (!active) return;
@@ -616,7 +642,7 @@ hipError_t launch_chain_persistent(const DevProblem *d_probs, const WorkItem *d_
 template <typename T, int G, int B>
 hipError_t launch_chain_eval(const DevProblem *d_probs, const double *coords, int n_rep, double centre,
                              double *forces, double *energy, hipStream_t stream) {
-    const int per = WG / G;
+    const int per = chain_reps_per_wg(G);
     const int nb = (n_rep + per - 1) / per;
     hipLaunchKernelGGL((chain_eval<T, G, B>), dim3(nb), dim3(WG), 0, stream, d_probs, coords, n_rep, centre, forces,
                        energy);
