@@ -33,7 +33,7 @@ __device__ __forceinline__ U4 philox(uint64_t seed, uint32_t c0, uint32_t c1, ui
 
 // Four standard normals per Philox block by Box-Muller, in the requested
 // precision.  fp64: u = (r + 1/2) 2^-32 (exact); fp32: u = (r>>9 + 1/2) 2^-23
-// (exact in fp32, hardware log2/sin/cos, whose argument is in turns).
+// (exact in fp32, hardware log2/sqrt/sin/cos; sin and cos take turns).
 template <typename T> struct Normal4;
 
 template <> struct Normal4<double> {
@@ -58,21 +58,28 @@ template <> struct Normal4<float> {
         const float m2ln2 = -2.0f * 0.69314718055994531f;
         float ua = ((float)(r.x >> 9) + 0.5f) * scale, ub = ((float)(r.y >> 9) + 0.5f) * scale;
         float uc = ((float)(r.z >> 9) + 0.5f) * scale, ud = ((float)(r.w >> 9) + 0.5f) * scale;
-        float ra = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
-        float rc = __builtin_sqrtf(m2ln2 * __builtin_amdgcn_logf(uc));
+        float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
+        float rc = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(uc));
         z[0] = ra * __builtin_amdgcn_cosf(ub); z[1] = ra * __builtin_amdgcn_sinf(ub);
         z[2] = rc * __builtin_amdgcn_cosf(ud); z[3] = rc * __builtin_amdgcn_sinf(ud);
     }
 };
 
 // ---------------------------------------------------------------------------
-// Reciprocal in the working precision: the hardware approximation in fp32,
-// the IEEE quotient in fp64.
+// Reciprocal and length in the working precision: the hardware instructions
+// (about 1 ulp) in fp32, IEEE division and square root in fp64.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_t(float x) { return __builtin_sqrtf(x); }
-__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+// |v| and 1/|v| from |v|^2
+__device__ __forceinline__ void len_inv(float r2, float &len, float &inv) {
+    inv = __builtin_amdgcn_rsqf(r2);
+    len = r2 * inv;
+}
+__device__ __forceinline__ void len_inv(double r2, double &len, double &inv) {
+    len = sqrt(r2);
+    inv = 1.0 / len;
+}
 
 // ---------------------------------------------------------------------------
 // Running log-sum-exp (m, S): ln sum_k exp(a_k) = m + ln S.

@@ -15,9 +15,12 @@
 //     j-beads rotate one lane per round through the group together with an
 //     accumulator of their reaction forces, which finally is pushed back to
 //     the owning lane (for even G the last round, which meets the opposite
-//     lane, is done from both sides instead).  Bonded terms read a two-bead halo from the
-//     neighbouring lanes.  Nothing leaves registers inside the step loop
-//     except the per-sample histogram increment (one u64 atomic).
+//     lane, is done from both sides instead).  Each bond and angle is
+//     computed once, by the lane owning its first or central bead, from a
+//     one-bead halo read from the neighbouring lanes, which read back the
+//     forces on their halo beads.  Inside the step loop nothing leaves
+//     registers except each sample's accumulator update and histogram count
+//     (LDS).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -185,8 +188,6 @@ __global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ prob
 // ===========================================================================
 template <typename T, int G, int B, bool ENERGY>
 struct ChainForce {
-    static constexpr int HALO = G > 1 ? 2 : 0;
-    static constexpr int L = B + 2 * HALO;   // local window of beads around the owned ones
 
     // Lennard-Jones between bead sets a (owned) and b; N3: also accumulate reaction on b.
     template <bool N3, bool MASK>
@@ -295,53 +296,52 @@ struct ChainForce {
             }
         }
 
-        // ---- bonded terms: slide along the local beads [gB - HALO, gB + B + HALO) ----
-        // Two bond vectors are live at a time; each bond and angle that touches an
-        // owned bead adds its gradient straight to the owned beads (a lane recomputes
-        // the one or two terms it shares with a neighbour lane).
-        T hx[2 * HALO + 1], hy[2 * HALO + 1], hz[2 * HALO + 1];   // halo beads (prev lane's last two, next lane's first two)
+        // ---- bonded terms, each computed once ----
+        // Local slots 0..B+1: slot 0 is the previous lane's last bead, slots 1..B
+        // the owned beads, slot B+1 the next lane's first bead.  A lane takes the
+        // bonds that start at an owned bead and the angles centred on owned
+        // beads; the forces these put on the two halo beads are read back by the
+        // lanes that own them.
+        T hpx = 0, hpy = 0, hpz = 0, hnx = 0, hny = 0, hnz = 0;   // halo beads
+        const int prev = solo ? me : gbase + (g > 0 ? g - 1 : 0);
+        const int next = solo ? me : gbase + (g + 1 < G ? g + 1 : G - 1);
         if constexpr (G > 1) {
-            const int prev = solo ? me : gbase + (g > 0 ? g - 1 : 0);
-            const int next = solo ? me : gbase + (g + 1 < G ? g + 1 : G - 1);
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                hx[hh] = pull_f(prev, px[B - 2 + hh]); hy[hh] = pull_f(prev, py[B - 2 + hh]); hz[hh] = pull_f(prev, pz[B - 2 + hh]);
-                hx[HALO + hh] = pull_f(next, px[hh]); hy[HALO + hh] = pull_f(next, py[hh]); hz[HALO + hh] = pull_f(next, pz[hh]);
-            }
+            hpx = pull_f(prev, px[B - 1]); hpy = pull_f(prev, py[B - 1]); hpz = pull_f(prev, pz[B - 1]);
+            hnx = pull_f(next, px[0]); hny = pull_f(next, py[0]); hnz = pull_f(next, pz[0]);
         }
-        const int ib = i0 - HALO;   // bead index of local slot 0
         const T kb = (T)P.k_bond, r0 = (T)P.r0, kth = (T)P.k_angle;
-        // position of local slot t (compile-time t)
-        auto slot = [&](int t, T &x, T &y, T &z) {
-            if (t < HALO) { x = hx[t]; y = hy[t]; z = hz[t]; }
-            else if (t < HALO + B) { x = px[t - HALO]; y = py[t - HALO]; z = pz[t - HALO]; }
-            else { x = hx[t - B]; y = hy[t - B]; z = hz[t - B]; }
+        auto slot = [&](int t, T &x, T &y, T &z) {   // position of local slot t (compile-time t)
+            if (t == 0) { x = hpx; y = hpy; z = hpz; }
+            else if (t <= B) { x = px[t - 1]; y = py[t - 1]; z = pz[t - 1]; }
+            else { x = hnx; y = hny; z = hnz; }
         };
-        auto add = [&](int t, T gx_, T gy_, T gz_) {   // force on local slot t if it is owned
-            if (t >= HALO && t < HALO + B) { fx[t - HALO] += gx_; fy[t - HALO] += gy_; fz[t - HALO] += gz_; }
+        T qpx = 0, qpy = 0, qpz = 0, qnx = 0, qny = 0, qnz = 0;   // forces on the halo beads
+        auto add = [&](int t, T gx_, T gy_, T gz_) {
+            if (t == 0) { qpx += gx_; qpy += gy_; qpz += gz_; }
+            else if (t <= B) { fx[t - 1] += gx_; fy[t - 1] += gy_; fz[t - 1] += gz_; }
+            else { qnx += gx_; qny += gy_; qnz += gz_; }
         };
         T ax = 0, ay = 0, az = 0, ail = 0;   // previous bond (t-1 -> t) and its inverse length
         bool avalid = false;
 #pragma unroll
-        for (int t = 0; t < L - 1; ++t) {
+        for (int t = 0; t <= B; ++t) {
             T x0, y0, z0, x1, y1, z1;
             slot(t, x0, y0, z0);
             slot(t + 1, x1, y1, z1);
             const T bx = x1 - x0, by = y1 - y0, bz = z1 - z0;
-            const T bl = sqrt_t(bx * bx + by * by + bz * bz);
-            const T bil = rcp_t(bl);
-            const int i = ib + t;
+            const int i = i0 - 1 + t;               // bead index of slot t
             const bool bvalid = i >= 0 && i + 1 < N;
-            // bond (t, t+1), k_b/2 (|b| - r0)^2: dU/db = k_b (|b| - r0) b/|b|
-            if (t + 1 >= HALO && t < HALO + B) {
+            // a bond outside the chain gets unit length so its masked terms stay finite
+            T bl, bil;
+            len_inv(bvalid ? bx * bx + by * by + bz * bz : (T)1, bl, bil);
+            if (t >= 1) {
+                // bond (t, t+1), k_b/2 (|b| - r0)^2: dU/db = k_b (|b| - r0) b/|b|
                 T gsc = kb * (bl - r0) * bil;
                 gsc = bvalid ? gsc : (T)0;
                 add(t, gsc * bx, gsc * by, gsc * bz);
                 add(t + 1, -gsc * bx, -gsc * by, -gsc * bz);
-                if (ENERGY && bvalid && t >= HALO) e_bond += 0.5 * (double)(kb * (bl - r0) * (bl - r0));
-            }
-            // angle between the previous bond a (t-1 -> t) and this bond b (t -> t+1), beads t-1, t, t+1
-            if (t >= 1 && t + 1 >= HALO && t - 1 < HALO + B) {
+                if (ENERGY && bvalid) e_bond += 0.5 * (double)(kb * (bl - r0) * (bl - r0));
+                // angle centred on slot t between bond a (t-1 -> t) and bond b (t -> t+1)
                 const bool valid = avalid && bvalid;
                 const T iab = ail * bil;
                 const T c = (ax * bx + ay * by + az * bz) * iab;
@@ -353,9 +353,17 @@ struct ChainForce {
                 add(t - 1, dax, day, daz);
                 add(t, dbx - dax, dby - day, dbz - daz);
                 add(t + 1, -dbx, -dby, -dbz);
-                if (ENERGY && valid && t - 1 >= HALO) e_ang += (double)(kth * ((T)1 - c));
+                if (ENERGY && valid) e_ang += (double)(kth * ((T)1 - c));
             }
             ax = bx; ay = by; az = bz; ail = bil; avalid = bvalid;
+        }
+        if constexpr (G > 1) {
+            // the next lane's slot-0 force is on our last bead, the previous lane's
+            // slot-(B+1) force on our first
+            const T lx = pull_f(next, qpx), ly = pull_f(next, qpy), lz = pull_f(next, qpz);
+            const T fx0 = pull_f(prev, qnx), fy0 = pull_f(prev, qny), fz0 = pull_f(prev, qnz);
+            if (g + 1 < G) { fx[B - 1] += lx; fy[B - 1] += ly; fz[B - 1] += lz; }
+            if (g > 0) { fx[0] += fx0; fy[0] += fy0; fz[0] += fz0; }
         }
 
         // ---- restraint k/2 (xi - centre)^2 on the pulled end ----
@@ -366,7 +374,7 @@ struct ChainForce {
                 const T dx = px[b] - (T)P.fix_x, dy = py[b] - (T)P.fix_y, dz = pz[b] - (T)P.fix_z;
                 T xi, ux, uy, uz;
                 if (P.rc_mode == 1) { xi = dz; ux = 0; uy = 0; uz = 1; }
-                else { xi = sqrt_t(dx * dx + dy * dy + dz * dz); const T ixi = rcp_t(xi); ux = dx * ixi; uy = dy * ixi; uz = dz * ixi; }
+                else { T ixi; len_inv(dx * dx + dy * dy + dz * dz, xi, ixi); ux = dx * ixi; uy = dy * ixi; uz = dz * ixi; }
                 const T fr = -(T)P.k * (xi - centre);
                 fx[b] += fr * ux; fy[b] += fr * uy; fz[b] += fr * uz;
                 if (ENERGY) e_res += 0.5 * P.k * (double)(xi - centre) * (double)(xi - centre);
