@@ -43,3 +43,32 @@ def test_adaptive_double_well_meets_overlap_target_and_quadrature():
     z = (res["dF_je"][-1] - exact[-1]) / res["dF_je_se"][-1]
     print(f"  dF_je end {res['dF_je'][-1]:.4f} exact {exact[-1]:.4f} z {z:.2f}", flush=True)
     assert abs(z) < 3.5
+
+
+def test_learned_placement_beats_uniform_windows_at_half_the_budget():
+    """What the trained surrogate gains: with a stiff restraint (k = 800) the 21
+    uniform windows of the double-well workload lie 4.5 sigma apart, their
+    forward work distributions barely overlap and JE misses the exact
+    dF(1.5) = 0 by several kT; placement by the surrogate at half the
+    replica-steps lands within the statistical error."""
+    print("case learned vs uniform 1d k=800", flush=True)
+    base = ppp_inputs.config_1d(n_replicas=256, n_steps=20000, precision="fp64", seed=5)
+    base["k"] = 800.0
+    base["n_blocks"] = 16
+    base["w_half_bins"] = 0
+    budget = 21 * 256 * 20000
+    uni, _ = ppp.run(base)
+    err_u = abs(uni["dF_je"][-1])                     # exact: F(1.5) = F(-1.5) by symmetry
+    ad = {"budget_replica_steps": budget // 2, "initial_windows": 11, "max_rounds": 5, "max_windows": 192,
+          "target_dl_over_sigma": 1.0, "train_iters": 600, "lr": 3e-3, "init_seed": 3,
+          "explore_replicas": 32, "explore_steps": 2000, "min_production_steps": 1000}
+    res, lam, used = ppp.ppp_adaptive_run(dict(base, n_steps=4000), ad)
+    err_l = abs(res["dF_je"][-1])
+    print(f"  uniform: max dl/sigma {np.nanmax(uni['dlambda_over_sigma']):.2f}, |dF err| {err_u:.3f} "
+          f"(se {uni['dF_je_se'][-1]:.3f}); learned: {len(lam)} windows, {used:.3g} replica-steps, "
+          f"max dl/sigma {np.nanmax(res['dlambda_over_sigma']):.2f}, |dF err| {err_l:.3f} "
+          f"(se {res['dF_je_se'][-1]:.3f})", flush=True)
+    assert used <= budget // 2
+    assert err_u > 1.0                                  # the uniform protocol fails here
+    assert err_l < 0.25 * err_u
+    assert err_l < 3.5 * res["dF_je_se"][-1] + 0.05
