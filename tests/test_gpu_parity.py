@@ -219,6 +219,29 @@ def test_checkpoint_resume_is_bit_identical():
         assert np.array_equal(full[key], part[key]), key
 
 
+def test_advancing_in_uneven_chunks_matches_one_run():
+    """The chain noise is drawn per group of four steps with deviates carried
+    between steps; advances that stop at every position inside a group must
+    rebuild the carried deviates and give the single run's results exactly."""
+    _say("case uneven chunks")
+    for precision in ("fp32", "fp64"):
+        prob = ppp_inputs.config_chain_small(10, n_replicas=30, n_steps=240, n_windows=3, precision=precision)
+        full, _ = ppp.run(prob)
+        h = ppp.ppp_create(prob)
+        try:
+            ws = ppp.workspace(h)
+            ppp.ppp_begin(h, ws)
+            for n in [1, 2, 3, 5, 6, 7, 9, 13] * 4:
+                ppp.ppp_advance(h, n)
+            ppp.ppp_advance(h, 10 ** 9)
+            ppp.ppp_finalize(h)
+            part = ppp.ppp_get_result(h, prob)
+        finally:
+            ppp.ppp_destroy(h)
+        for key in ("dF_je", "dF_fluct", "xi_mean", "xi_std", "xi_hist", "n_samples"):
+            assert np.array_equal(full[key], part[key]), (precision, key)
+
+
 def test_frozen_replicas_are_counted():
     _say("case blowup")
     prob = ppp_inputs.config_chain_small(10, n_replicas=16, n_steps=100, n_windows=3, precision="fp32")
