@@ -34,8 +34,12 @@ __device__ __forceinline__ double centre_at(const DevProblem &P, double lam, int
     return P.xi_start + (lam - P.xi_start) * ((double)n / (double)P.n_pull);
 }
 
-__device__ __forceinline__ bool sample_now(const DevProblem &P, int64_t n) {
-    return n > P.n_equil && ((n - P.n_equil) % P.sample_every) == 0;
+// First step after `after` at which xi is sampled (steps n > n_equil with
+// n - n_equil a multiple of sample_every); the loops then count up to it
+// instead of taking a 64-bit remainder every step.
+__device__ __forceinline__ int64_t next_sample_after(const DevProblem &P, int64_t after) {
+    if (after < P.n_equil) return P.n_equil + P.sample_every;
+    return P.n_equil + ((after - P.n_equil) / P.sample_every + 1) * P.sample_every;
 }
 
 // Folds one sample xi of window w into the replica's accumulator.  The
@@ -146,6 +150,7 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
     bool alive = acc[A_BLOWN] == 0.0;
     T z[4];
     uint32_t zblock = 0xFFFFFFFFu;
+    int64_t n_sample = next_sample_after(P, step_begin);
     for (int64_t n = step_begin + 1; n <= n_end && alive; ++n) {
         const T F = force_1d<T>(P, x, (T)centre_at(P, lam_w, n - 1));
         const uint32_t blk = (uint32_t)(n >> 2);
@@ -155,7 +160,8 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
         else x = x + mu_dt * F + amp * eta;
         eta_prev = eta;
         if (record && n <= 100000) traj[n] = (double)x;
-        if (sample_now(P, n)) {
+        if (n == n_sample) {
+            n_sample += P.sample_every;
             const double xi = (double)x;
             if (!isfinite(xi) || fabs(xi) > P.xi_bound) { acc[A_BLOWN] = 1.0; alive = false; break; }
             accumulate(P, lam, w, xi, acc, hist, lhist);
@@ -348,8 +354,9 @@ struct ChainForce {
                 const T ca = c * ail * ail, cb = c * bil * bil;
                 const T kk = valid ? kth : (T)0;
                 // dU/da = -k (b/(|a||b|) - c a/|a|^2), dU/db = -k (a/(|a||b|) - c b/|b|^2)
-                const T dax = -kk * (bx * iab - ca * ax), day = -kk * (by * iab - ca * ay), daz = -kk * (bz * iab - ca * az);
-                const T dbx = -kk * (ax * iab - cb * bx), dby = -kk * (ay * iab - cb * by), dbz = -kk * (az * iab - cb * bz);
+                const T s_ab = -kk * iab, s_a = kk * ca, s_b = kk * cb;
+                const T dax = s_ab * bx + s_a * ax, day = s_ab * by + s_a * ay, daz = s_ab * bz + s_a * az;
+                const T dbx = s_ab * ax + s_b * bx, dby = s_ab * ay + s_b * by, dbz = s_ab * az + s_b * bz;
                 add(t - 1, dax, day, daz);
                 add(t, dbx - dax, dby - day, dbz - daz);
                 add(t + 1, -dbx, -dby, -dbz);
@@ -460,6 +467,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     const T c1 = (T)P.c1;
     const T hm = (T)(0.5 * P.dt * P.inv_mass);
     const T c2sd = (T)P.c2sd;
+    int64_t n_sample = next_sample_after(P, step_begin);
     for (int64_t n = step_begin + 1; n <= n_end; ++n) {
         if (!alive) break;
 #pragma unroll
@@ -488,7 +496,8 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                     o[0] = (double)px[b]; o[1] = (double)py[b]; o[2] = (double)pz[b];
                 }
         }
-        if (sample_now(P, n)) {
+        if (n == n_sample) {
+            n_sample += P.sample_every;
             bool ok = true;
 #pragma unroll
             for (int b = 0; b < B; ++b)
