@@ -258,47 +258,61 @@ struct ChainForce {
             }
         }
         // ---- Lennard-Jones between lanes: rotate the j-beads through the group ----
+        // Round r meets the beads of lane g - r.  Rounds 1 .. (G-1)/2 meet every
+        // lane pair once and keep the reactions, which travel with the beads and
+        // go back to their owner at the end; for even G round G/2 meets the
+        // opposite lane, from both sides.  Only round 1 meets sequence neighbours
+        // (pairs |i-j| <= 2 are excluded), so only it takes the masked routine.
         if constexpr (G > 1) {
+            constexpr int R_N3 = (G - 1) / 2;
+            constexpr bool HALF = (G % 2) == 0;
             T qx[B], qy[B], qz[B], gx[B], gy[B], gz[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) { qx[b] = px[b]; qy[b] = py[b]; qz[b] = pz[b]; gx[b] = 0; gy[b] = 0; gz[b] = 0; }
-            int jo = g;                 // lane that owns the beads now held in q
-            int jo_n3 = g;
             const int src = solo ? me : gbase + ((g + G - 1) % G);
-#pragma unroll 1
-            for (int r = 1; r <= G / 2; ++r) {
+            auto pull_q = [&]() {
 #pragma unroll
                 for (int b = 0; b < B; ++b) { qx[b] = pull_f(src, qx[b]); qy[b] = pull_f(src, qy[b]); qz[b] = pull_f(src, qz[b]); }
-                jo = pull_i(src, jo);
-                // rounds that meet every lane pair once keep the reactions; the round
-                // meeting the opposite lane of an even group is done from both sides
-                const bool n3 = 2 * r < G;
-                if (n3 && r > 1) {
-#pragma unroll
-                    for (int b = 0; b < B; ++b) { gx[b] = pull_f(src, gx[b]); gy[b] = pull_f(src, gy[b]); gz[b] = pull_f(src, gz[b]); }
-                }
-                const int dl = g - jo;
-                const bool near = (dl == 1 || dl == -1);
-                const bool any_near = __ballot(near) != 0ull;
+            };
+            // round 1
+            pull_q();
+            {
                 double e_r = 0.0;
-                if (n3) {
-                    jo_n3 = jo;
-                    if (any_near) lj_block<true, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
-                    else lj_block<true, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                const int jb = ((g + G - 1) % G) * B;
+                if constexpr (R_N3 >= 1) {
+                    lj_block<true, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jb, lA, lB, rc2, e_r);
                     e_lj += e_r;
-                } else {
-                    if (any_near) lj_block<false, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
-                    else lj_block<false, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jo * B, lA, lB, rc2, e_r);
+                } else {   // G == 2: the neighbour is also the opposite lane
+                    lj_block<false, true>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, jb, lA, lB, rc2, e_r);
                     e_lj += 0.5 * e_r;   // each such pair is seen from both lanes
                 }
             }
-            if constexpr (G > 2) {
-                // reaction forces go back to the lane owning those beads
-                const int dst = solo ? me : gbase + jo_n3;
+            // rounds 2 .. R_N3
+#pragma unroll 1
+            for (int r = 2; r <= R_N3; ++r) {
+                pull_q();
+#pragma unroll
+                for (int b = 0; b < B; ++b) { gx[b] = pull_f(src, gx[b]); gy[b] = pull_f(src, gy[b]); gz[b] = pull_f(src, gz[b]); }
+                double e_r = 0.0;
+                lj_block<true, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, 0, lA, lB, rc2, e_r);
+                e_lj += e_r;
+            }
+            if constexpr (R_N3 >= 1) {
+                // the reactions belong to lane g - R_N3
+                const int dst = solo ? me : gbase + ((g + G - R_N3) % G);
 #pragma unroll
                 for (int b = 0; b < B; ++b) {
                     fx[b] += push_f(dst, gx[b]); fy[b] += push_f(dst, gy[b]); fz[b] += push_f(dst, gz[b]);
                 }
+            }
+            if constexpr (HALF && G > 2) {
+                // round G/2: the opposite lane, its beads pulled directly
+                const int opp = solo ? me : gbase + ((g + G / 2) % G);
+#pragma unroll
+                for (int b = 0; b < B; ++b) { qx[b] = pull_f(opp, px[b]); qy[b] = pull_f(opp, py[b]); qz[b] = pull_f(opp, pz[b]); }
+                double e_r = 0.0;
+                lj_block<false, false>(P, px, py, pz, qx, qy, qz, fx, fy, fz, gx, gy, gz, i0, 0, lA, lB, rc2, e_r);
+                e_lj += 0.5 * e_r;
             }
         }
 
