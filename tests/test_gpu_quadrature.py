@@ -1,0 +1,72 @@
+"""Final dF of GPU runs against exact quadrature of the restrained partition
+function (needs an MI355X): the 1-D double-well workload at full size, and the
+chains with N = 2 and N = 3 beads, where no Lennard-Jones pair exists and the
+radial (N = 2) or three-dimensional (N = 3) integral is exact.  JE is unbiased
+up to sampling and time-step error, so it must land within 3 jackknife
+standard errors; fp32 forces with fp64 accumulation are held to the same bar."""
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1105_4840_amd as ppp
+import ppp_inputs
+from oracle import quadrature
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _z(res, exact):
+    return (res["dF_je"][1:] - exact[1:]) / res["dF_je_se"][1:]
+
+
+def test_double_well_workload_against_quadrature():
+    """21 windows x 256 replicas x 20000 LM steps, fp64 (the 1-D workload itself)."""
+    _say("case quadrature 1d workload")
+    prob = ppp_inputs.config_1d()
+    prob["n_blocks"] = 16
+    res, _ = ppp.run(prob)
+    F, mu, var = quadrature.restrained_1d(quadrature.double_well(), prob["lambda"], prob["k"], prob["kT"])
+    exact = F - F[0]
+    z = _z(res, exact)
+    _say(f"  dF_je end {res['dF_je'][-1]:.4f} +- {res['dF_je_se'][-1]:.4f} (exact {exact[-1]:.4f}); max |z| {np.max(np.abs(z)):.2f}")
+    assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 4.0
+    # window moments against the exact ones
+    zm = (res["xi_mean"] - mu) / (res["xi_std"] / np.sqrt(res["n_samples"] / 10.0))
+    assert np.max(np.abs(zm)) < 5.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_beads", [2, 3])
+def test_short_chains_against_quadrature(n_beads, precision):
+    _say(f"case quadrature chain N={n_beads} {precision}")
+    prob = ppp_inputs.config_chain_small(n_beads, n_replicas=512, n_steps=20000, n_windows=8, precision=precision)
+    prob["lambda"] = list(np.linspace(0.6, 1.6, 8) if n_beads == 2 else np.linspace(1.2, 2.2, 8))
+    prob["n_blocks"] = 32
+    prob["w_half_bins"] = 0
+    res, _ = ppp.run(prob)
+    if n_beads == 2:
+        F, mu, var = quadrature.chain2(prob["lambda"], prob["k"], prob["kT"], prob["k_bond"], prob["r0"])
+    else:
+        F, mu, var = quadrature.chain3(prob["lambda"], prob["k"], prob["kT"], prob["k_bond"], prob["r0"], prob["k_angle"])
+    exact = F - F[0]
+    z = _z(res, exact)
+    _say(f"  dF_je end {res['dF_je'][-1]:.4f} +- {res['dF_je_se'][-1]:.4f} (exact {exact[-1]:.4f}); "
+         f"z {np.round(z, 2)}")
+    assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 3.5
+    # Eq. 13 with exact moments is what dF_gauss estimates; its sampled value sits near it
+    fl, g = quadrature.estimator_expectations(prob["lambda"], mu, var, prob["k"], prob["kT"])
+    assert abs(res["dF_gauss"][-1] - g[-1]) < 3.5 * res["dF_gauss_se"][-1] + 1e-3
