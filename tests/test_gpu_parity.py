@@ -144,7 +144,7 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
     for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com", "dF_unc", "dF_rev"):
         assert np.max(np.abs(res[key] - ref[key])) < prof_tol * (1 + np.max(np.abs(ref[key]))), key
     for key in ("dF_je_se", "dF_fluct_se", "dF_gauss_se", "dF_com_se"):
-        assert np.allclose(res[key][1:], ref[key][1:], rtol=1e-7, atol=1e-12), key
+        assert np.allclose(res[key][1:], ref[key][1:], rtol=1e-7, atol=1e-12, equal_nan=True), key
     for key in ("kish_frac", "overlap_ovl", "dlambda_over_sigma", "dlambda_over_reach"):
         assert np.allclose(res[key], ref[key][:s - 1], rtol=1e-9, atol=1e-12), key
     assert np.array_equal(res["criterion_ok"].astype(bool), ref["criterion_ok"][:s - 1])
@@ -190,6 +190,54 @@ def test_run_parity_fp64(case):
     xi, kept, _ = oracle.run(prob)
     ref = estimators.estimate(prob, xi, kept)
     _compare_runs(prob, res, ref)
+
+
+def _edge_case(name):
+    if name == "smallest":          # N = 2, two windows, one replica, one histogram bin, no App. C
+        p = ppp_inputs.config_chain_small(2, n_replicas=1, n_steps=500, n_windows=2, precision="fp64")
+        p.update({"xi_nbins": 1, "xi_min": 0.0, "xi_bin": 10.0, "w_half_bins": 0, "n_blocks": 1})
+    elif name == "decreasing":      # pulling towards smaller lambda
+        p = ppp_inputs.config_chain_small(3, n_replicas=40, n_steps=800, n_windows=5, precision="fp64")
+        p["lambda"] = p["lambda"][::-1]
+        p["w_half_bins"] = 2000
+        p["w_bin"] = 0.05
+    elif name == "every-step":      # sample every step from the first one
+        p = ppp_inputs.config_1d(n_replicas=50, n_steps=600, n_windows=5)
+        p.update({"n_equil": 0, "sample_every": 1, "w_half_bins": 2000})
+    elif name == "narrow-histogram":  # most samples fall outside the histogram
+        p = ppp_inputs.config_chain_small(10, n_replicas=30, n_steps=400, n_windows=4, precision="fp64")
+        lo = p["lambda"][1]
+        p.update({"xi_min": lo, "xi_bin": 0.01, "xi_nbins": 50, "w_half_bins": 1000, "w_bin": 0.05})
+    else:
+        raise ValueError(name)
+    return p
+
+
+@pytest.mark.parametrize("name", ["smallest", "decreasing", "every-step", "narrow-histogram"])
+def test_edge_case_parity_fp64(name):
+    _say(f"case edge {name}")
+    prob = _edge_case(name)
+    res, _ = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+    if name == "narrow-histogram":
+        assert res["xi_under_over"].sum() > 0
+
+
+def test_run_without_samples():
+    """Too few steps for any sample: counts are zero and every estimate is
+    non-finite, on both sides."""
+    _say("case no samples")
+    prob = ppp_inputs.config_chain_small(4, n_replicas=8, n_steps=50, n_windows=3, precision="fp64")
+    prob.update({"n_equil": 45, "sample_every": 10})
+    res, _ = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    assert np.all(res["n_samples"] == 0) and np.all(ref["n_samples"] == 0)
+    assert np.all(res["xi_hist"] == 0)
+    for key in ("dF_je", "dF_fluct", "dF_gauss"):
+        assert not np.any(np.isfinite(res[key][1:])) and not np.any(np.isfinite(ref[key][1:])), key
 
 
 def test_checkpoint_resume_is_bit_identical():
