@@ -217,6 +217,9 @@ def main():
                     help="dF error at equal budget, uniform vs learned windows (32-bead chain)")
     ap.add_argument("--ref-steps", type=int, default=40000)
     ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
+    ap.add_argument("--sequential", action="store_true",
+                    help="run the workload with the sequential pulling protocol (each replica runs the "
+                         "windows one after another; same replica-steps)")
     ap.add_argument("--profile-launches", type=int, default=0,
                     help="with --chunk: stop after this many advances and print no bench line "
                          "(for counter collection on one launch of a long workload)")
@@ -246,19 +249,24 @@ def main():
         batch_bench(args, desc)
         return
     prob = getattr(ppp_inputs, fn)()
+    if args.sequential:
+        prob["sequential"] = True
     h = ppp.ppp_create(prob)
     ws = ppp.workspace(h)
     rs_per_run = len(prob["lambda"]) * prob["n_replicas"] * prob["n_steps"]
+
+    # steps each replica takes (all windows in turn for the sequential protocol)
+    steps_total = prob["n_steps"] * (len(prob["lambda"]) if args.sequential else 1)
 
     def one_run():
         if args.chunk > 0:
             ppp.ppp_begin(h, ws, stream)
             done = 0
-            while done < prob["n_steps"]:
+            while done < steps_total:
                 ppp.ppp_advance(h, args.chunk, stream)
                 torch.cuda.synchronize()
                 done = ppp.ppp_steps_done(h)
-                print(f"# progress {done}/{prob['n_steps']} steps", file=sys.stderr, flush=True)
+                print(f"# progress {done}/{steps_total} steps", file=sys.stderr, flush=True)
             ppp.ppp_finalize(h, stream)
         else:
             ppp.ppp_run(h, ws, stream)
@@ -320,7 +328,9 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if prob.get("precision") == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "windows": len(prob["lambda"]),
+        "config": {"workload": args.workload + ("-sequential" if args.sequential else ""),
+                   "protocol": "sequential" if args.sequential else "parallel",
+                   "description": desc, "windows": len(prob["lambda"]),
                    "replicas_per_window": prob["n_replicas"], "relaxation_steps": prob["n_steps"],
                    "replica_steps_per_step": rs_per_run, "parallelism": "1 GPU"},
         "kernel_replica_steps_per_s": rs_per_launch / avg_sim_s,

@@ -105,8 +105,22 @@ typedef struct {
     int32_t w_half_bins;         /* M >= 0: 2M+1 work bins; 0 disables App. C */
     int32_t n_jack_blocks;       /* jackknife blocks B in [0, 4096] (0: 32); above n_replicas: n_replicas */
     double xi_bound;             /* |xi| above this freezes a replica (<= 0: 1e4) */
-    uint32_t flags;              /* reserved, must be 0 */
+    uint32_t flags;              /* 0 or PPP_FLAG_SEQUENTIAL */
 } ppp_problem;
+
+/* Sequential pulling protocol (Sec. III(i), Fig. 1b) instead of the parallel
+ * one: each of the n_replicas replicas starts from x_o in window 1, relaxes
+ * n_steps there, and continues from its last state in window 2, and so on to
+ * window s (s * n_steps steps per replica, the same replica-steps as the
+ * parallel protocol).  n_equil and sample_every apply inside every window; a
+ * linear pull (n_pull) applies to window 1 only.  The per-window records and
+ * every estimator are those of the parallel protocol.  A replica frozen in one
+ * window stays frozen in the later ones.  Noise: replica r uses the counters
+ * of replica r of window 1 in the parallel protocol, with the step counted
+ * from the start of window 1, so window 1 gives the same samples in both
+ * protocols.  Not available for batched or adaptive runs, nor for
+ * ppp_trajectory. */
+#define PPP_FLAG_SEQUENTIAL 1u
 
 /* Caller-owned host output buffers; any pointer may be NULL (not wanted).
  * s = n_windows, K = xi_nbins, M = w_half_bins.  Profiles are relative to
@@ -161,7 +175,8 @@ typedef struct ppp_handle ppp_handle;
  * monotone or non-finite, k, kT, dt <= 0, n_replicas < 1, sample_every < 1,
  * n_equil < 0 or >= n_steps, K < 1, xi_bin <= 0, w_bin <= 0 with M > 0,
  * chain with n_beads < 2 or > PPP_MAX_BEADS, non-positive mass or bond
- * length, flags != 0.  *out is NULL on failure. */
+ * length, unknown flags, or a sequential run of more than 2^32 - 1 steps per
+ * replica.  *out is NULL on failure. */
 ppp_status ppp_create(const ppp_problem *p, ppp_handle **out);
 
 /* Batched form (uneven chains, windows, replicas, steps): all problems run in

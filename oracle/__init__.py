@@ -46,6 +46,7 @@ class OracleProblem(ctypes.Structure):
         ("init_coords", ctypes.POINTER(ctypes.c_double)),
         ("xi_bound", ctypes.c_double),
         ("n_pull", ctypes.c_int64),
+        ("sequential", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ class _Problem:
             init_coords=None if self.init is None else _dp(self.init),
             xi_bound=float(prob.get("xi_bound", 1.0e4)),
             n_pull=int(prob.get("n_pull", 0)),
+            sequential=1 if prob.get("sequential", False) else 0,
         )
 
     def ref(self):

@@ -53,6 +53,7 @@ typedef struct {
     const double *init_coords; /* chain: [3 N]; 1-D: [1]; NULL: default x_o */
     double xi_bound;        /* |xi| above this (or non-finite state) freezes a replica */
     int64_t n_pull;         /* steps over which the centre moves from xi(x_o) to lambda_i (0: switched on at once) */
+    int32_t sequential;     /* 1: sequential pulling protocol (Sec. III(i)) instead of the parallel one */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -338,6 +339,102 @@ static int64_t run_replica_chain(const oracle_problem *p, int window, int replic
     return kept;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sequential pulling protocol (Sec. III(i)): one simulation per replica     */
+/* that sets the restraint centre to lambda_1, lambda_2, ... lambda_s in      */
+/* turn, relaxing n_steps at each and recording xi there (burn-in n_equil and */
+/* the record interval restart in every window).  Steps are counted from the  */
+/* start of window 1 and the noise is that of replica `replica` of window 1   */
+/* of the parallel protocol, so window 1 repeats the parallel protocol's.     */
+/* The linear pull (n_pull) applies to window 1.  A replica that blows up     */
+/* keeps no sample from that window on.  Its records go to rows               */
+/* w * n_replicas + replica of xi_out / n_kept, as in the parallel protocol.  */
+/* ------------------------------------------------------------------------ */
+static void run_sequential_1d(const oracle_problem *p, int replica, double *xi_out, int64_t *n_kept, int64_t S)
+{
+    const uint32_t gid = (uint32_t)replica;
+    double x = p->init_coords ? p->init_coords[0] : p->lambda[0];
+    const double x_start = x;
+    const double mu = p->mobility;
+    double eta_prev = eta_1d(p->seed, gid, 0);
+    int frozen = 0;
+    for (int w = 0; w < p->n_windows; ++w) {
+        const int64_t row = (int64_t)w * p->n_replicas + replica;
+        int64_t kept = 0;
+        for (int64_t t = 1; t <= p->n_steps && !frozen; ++t) {
+            const int64_t n = (int64_t)w * p->n_steps + t;
+            const double centre = (w == 0) ? centre_at(p, x_start, p->lambda[0], t - 1) : p->lambda[w];
+            double F;
+            oracle_pot1d(p, x, centre, &F);
+            double eta = eta_1d(p->seed, gid, n);
+            if (p->integrator_1d == 0)
+                x = x + mu * p->dt * F + sqrt(0.5 * mu * p->kT * p->dt) * (eta_prev + eta);
+            else
+                x = x + mu * p->dt * F + sqrt(2.0 * mu * p->kT * p->dt) * eta;
+            eta_prev = eta;
+            if (sample_now(p, t)) {
+                if (!isfinite(x) || fabs(x) > p->xi_bound) { frozen = 1; break; }
+                xi_out[row * S + kept++] = x;
+            }
+        }
+        n_kept[row] = kept;
+    }
+}
+
+static void run_sequential_chain(const oracle_problem *p, int replica, double *xi_out, int64_t *n_kept, int64_t S)
+{
+    const int N = p->n_beads;
+    const uint32_t gid = (uint32_t)replica;
+    double *r = (double *)malloc(sizeof(double) * 3 * N);
+    double *v = (double *)calloc(3 * N, sizeof(double));
+    double *f = (double *)malloc(sizeof(double) * 3 * N);
+    if (p->init_coords) memcpy(r, p->init_coords, sizeof(double) * 3 * N);
+    else oracle_default_helix(N, p->r0, r);
+    const double sd_v = sqrt(p->kT / p->mass);
+    for (int i = 1; i < N; ++i) {
+        double z[4];
+        oracle_normals4(p->seed, gid, 0u, (uint32_t)i, 0u, z);
+        for (int c = 0; c < 3; ++c) v[3 * i + c] = sd_v * z[c];
+    }
+    const double xi_start = chain_xi(p, r);
+    const double h = 0.5 * p->dt;
+    const double c1 = exp(-p->gamma * p->dt);
+    const double c2 = sqrt(1.0 - c1 * c1);
+    int frozen = 0;
+    for (int w = 0; w < p->n_windows; ++w) {
+        const int64_t row = (int64_t)w * p->n_replicas + replica;
+        const double lam = p->lambda[w];
+        int64_t kept = 0;
+        /* the restraint moves to lambda_w: forces of the new Hamiltonian */
+        oracle_chain_forces(p, r, (w == 0) ? centre_at(p, xi_start, lam, 0) : lam, f, NULL);
+        for (int64_t t = 1; t <= p->n_steps && !frozen; ++t) {
+            const int64_t n = (int64_t)w * p->n_steps + t;
+            for (int i = 1; i < N; ++i) {
+                double z[4];
+                oracle_normals4(p->seed, gid, (uint32_t)n, (uint32_t)i, 0u, z);
+                for (int c = 0; c < 3; ++c) {
+                    int q = 3 * i + c;
+                    v[q] += h * f[q] / p->mass;
+                    r[q] += h * v[q];
+                    v[q] = c1 * v[q] + c2 * sd_v * z[c];
+                    r[q] += h * v[q];
+                }
+            }
+            oracle_chain_forces(p, r, (w == 0) ? centre_at(p, xi_start, lam, t) : lam, f, NULL);
+            for (int q = 3; q < 3 * N; ++q) v[q] += h * f[q] / p->mass;
+            if (sample_now(p, t)) {
+                int finite = 1;
+                for (int q = 0; q < 3 * N; ++q) if (!isfinite(r[q])) finite = 0;
+                double xi = chain_xi(p, r);
+                if (!finite || !isfinite(xi) || fabs(xi) > p->xi_bound) { frozen = 1; break; }
+                xi_out[row * S + kept++] = xi;
+            }
+        }
+        n_kept[row] = kept;
+    }
+    free(r); free(v); free(f);
+}
+
 /* Runs every replica of every window.  xi_out is [n_windows*n_replicas][S]
  * with S = oracle_samples_per_replica(p); n_kept is [n_windows*n_replicas].
  * Returns the number of host threads used. */
@@ -355,12 +452,20 @@ int oracle_run(const oracle_problem *p, double *xi_out, int64_t *n_kept, int n_t
 #pragma omp single
         used = omp_get_num_threads();
 #endif
+        if (p->sequential) {
 #pragma omp for schedule(dynamic, 1)
-        for (int64_t g = 0; g < total; ++g) {
-            int window = (int)(g / p->n_replicas), replica = (int)(g % p->n_replicas);
-            double *dst = xi_out + g * S;
-            n_kept[g] = (p->model == 0) ? run_replica_1d(p, window, replica, dst, NULL, 0)
-                                        : run_replica_chain(p, window, replica, dst, NULL, 0);
+            for (int r = 0; r < p->n_replicas; ++r) {
+                if (p->model == 0) run_sequential_1d(p, r, xi_out, n_kept, S);
+                else run_sequential_chain(p, r, xi_out, n_kept, S);
+            }
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t g = 0; g < total; ++g) {
+                int window = (int)(g / p->n_replicas), replica = (int)(g % p->n_replicas);
+                double *dst = xi_out + g * S;
+                n_kept[g] = (p->model == 0) ? run_replica_1d(p, window, replica, dst, NULL, 0)
+                                            : run_replica_chain(p, window, replica, dst, NULL, 0);
+            }
         }
     }
     return used;

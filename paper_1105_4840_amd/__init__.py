@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libppp.so")
 
 PPP_OK, PPP_E_INVALID_ARG, PPP_E_OUT_OF_MEMORY, PPP_E_DEVICE, PPP_E_NUMERICAL, PPP_E_STATE, PPP_E_UNSUPPORTED = range(7)
+PPP_FLAG_SEQUENTIAL = 1
 PPP_MLP_HIDDEN = 64
 PPP_MLP_PARAMS = 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -193,7 +194,7 @@ def make_problem(prob: dict):
     p.xi_min = float(prob["xi_min"]); p.xi_bin = float(prob["xi_bin"]); p.xi_nbins = int(prob["xi_nbins"])
     p.w_bin = float(prob.get("w_bin", 0.01)); p.w_half_bins = int(prob.get("w_half_bins", 0))
     p.n_jack_blocks = int(prob.get("n_blocks", 0)); p.xi_bound = float(prob.get("xi_bound", 1.0e4))
-    p.flags = int(prob.get("flags", 0))
+    p.flags = int(prob.get("flags", 0)) | (PPP_FLAG_SEQUENTIAL if prob.get("sequential", False) else 0)
     return p, (lam, init)
 
 

@@ -46,7 +46,7 @@ struct DevProblem {
     int32_t xi_nbins, w_half_bins;
     int32_t sample_every;
     int32_t variant_lanes, variant_beads;   // chain kernel shape (G lanes x B beads per lane)
-    int32_t pad0;
+    int32_t sequential;     // 1: sequential pulling protocol (windows one after another per replica)
     int64_t n_steps, n_equil, n_pull;
     uint64_t seed;
     double k, kT, beta, dt;

@@ -134,7 +134,10 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
     if (p->w_half_bins < 0 || p->w_half_bins > 50000000) { msg = "w_half_bins out of range"; return PPP_E_INVALID_ARG; }
     if (p->w_half_bins > 0 && !finite_pos(p->w_bin)) { msg = "w_bin must be > 0"; return PPP_E_INVALID_ARG; }
     if (p->n_jack_blocks < 0 || p->n_jack_blocks > 4096) { msg = "n_jack_blocks must be in [0, 4096]"; return PPP_E_INVALID_ARG; }
-    if (p->flags != 0) { msg = "flags must be 0"; return PPP_E_INVALID_ARG; }
+    if ((p->flags & ~PPP_FLAG_SEQUENTIAL) != 0) { msg = "unknown flags"; return PPP_E_INVALID_ARG; }
+    if ((p->flags & PPP_FLAG_SEQUENTIAL) && (int64_t)p->n_windows * p->n_steps > 0xffffffffLL) {
+        msg = "a sequential run must have fewer than 2^32 steps per replica"; return PPP_E_INVALID_ARG;
+    }
     if (p->precision != PPP_FP32_FORCES && p->precision != PPP_FP64) { msg = "unknown precision"; return PPP_E_INVALID_ARG; }
     if (p->model == PPP_MODEL_1D) {
         const ppp_pot1d &q = p->pot1d;
@@ -250,6 +253,7 @@ ppp_status build_problem(const ppp_problem *p, ProblemHost &ph, const std::vecto
     d.variant_lanes = ph.G;
     d.variant_beads = ph.B;
     d.n_steps = p->n_steps;
+    d.sequential = (p->flags & PPP_FLAG_SEQUENTIAL) ? 1 : 0;
     d.n_equil = p->n_equil;
     d.n_pull = p->n_pull;
     d.seed = p->seed;
@@ -309,6 +313,12 @@ int64_t layout_problem(ProblemHost &ph, int64_t at) {
     return at;
 }
 
+// Steps each replica takes: n_steps, or n_steps in every window one after
+// another for the sequential protocol.
+int64_t total_steps(const ProblemHost &ph) {
+    return ph.dev.sequential ? (int64_t)ph.dev.n_windows * ph.dev.n_steps : ph.dev.n_steps;
+}
+
 int reps_per_item(const ProblemHost &ph) { return ph.dev.model == PPP_MODEL_CHAIN ? chain_reps_per_wg(ph.G) : WG; }
 
 // Work items of one problem.  Per window (every item inside one window), or,
@@ -324,7 +334,11 @@ void make_items(ProblemHost &ph, int prob_index, std::vector<WorkItem> &items, b
     const int64_t span_windows = (per - 1) / R + 2;   // a run of `per` replicas touches at most this many
     const bool span = allow_span && ph.dev.model == PPP_MODEL_CHAIN && R % per != 0 &&
                       span_windows * ph.dev.xi_nbins <= kLdsHistCap;
-    if (span) {
+    if (ph.dev.sequential) {
+        // the replicas of window 1; every window is run by the same items in turn
+        for (int r = 0; r < ph.dev.n_replicas; r += per)
+            items.push_back(WorkItem{prob_index, 0, r, std::min(per, ph.dev.n_replicas - r)});
+    } else if (span) {
         for (int64_t g = 0; g < total; g += per) {
             const int n = (int)std::min<int64_t>(per, total - g);
             items.push_back(WorkItem{prob_index, (int)(g / R), (int)(g % R), n});
@@ -390,8 +404,21 @@ ppp_status launch_items(ppp_handle *h, const ProblemHost &ph, int64_t b, int64_t
                         int64_t traj_rep, int first, int count) {
     const int64_t nk = (int64_t)ph.item_windows * ph.dev.xi_nbins;
     const int cap = nk <= kLdsHistCap ? (int)nk : 0;
-    HIPCHK(h, launch_sim(d_probs(h), d_items(h) + first, count, h->ws, b, e, ph.dev.model, ph.dev.precision, ph.G,
-                         ph.B, traj, traj_rep, cap, st));
+    if (!ph.dev.sequential) {
+        HIPCHK(h, launch_sim(d_probs(h), d_items(h) + first, count, h->ws, b, e, ph.dev.model, ph.dev.precision, ph.G,
+                             ph.B, traj, traj_rep, cap, st));
+        return PPP_OK;
+    }
+    // sequential protocol: one launch per window touched, so a launch never
+    // crosses a window boundary (the kernel takes the window from its first step)
+    const int64_t T = ph.dev.n_steps;
+    int64_t at = b;
+    do {
+        const int64_t stop = std::min(e, (at / T + 1) * T);
+        HIPCHK(h, launch_sim(d_probs(h), d_items(h) + first, count, h->ws, at, stop, ph.dev.model, ph.dev.precision,
+                             ph.G, ph.B, traj, traj_rep, cap, st));
+        at = stop;
+    } while (at < e);
     return PPP_OK;
 }
 
@@ -486,11 +513,13 @@ ppp_status do_advance(ppp_handle *h, int64_t n, hipStream_t st) {
     if (!h->begun) return fail(h, PPP_E_STATE, "advance before begin");
     if (n < 0) return fail(h, PPP_E_INVALID_ARG, "n_steps must be >= 0");
     int64_t maxsteps = 0;
-    for (auto &ph : h->probs) maxsteps = std::max(maxsteps, ph.dev.n_steps);
+    for (auto &ph : h->probs) maxsteps = std::max(maxsteps, total_steps(ph));
     const int64_t e = std::min(maxsteps, h->steps_done + n);
     if (e <= h->steps_done) return PPP_OK;
     for (auto &ph : h->probs) {
-        ppp_status s = launch_items(h, ph, h->steps_done, e, st, nullptr, -1, ph.first_item, ph.n_items);
+        const int64_t pe = std::min(e, total_steps(ph));
+        if (pe <= h->steps_done) continue;
+        ppp_status s = launch_items(h, ph, h->steps_done, pe, st, nullptr, -1, ph.first_item, ph.n_items);
         if (s != PPP_OK) return s;
     }
     h->steps_done = e;
@@ -501,11 +530,20 @@ ppp_status do_advance(ppp_handle *h, int64_t n, hipStream_t st) {
 
 ppp_status do_finalize(ppp_handle *h, hipStream_t st) {
     if (!h->begun) return fail(h, PPP_E_STATE, "finalize before begin");
-    if (h->steps_done == 0 && !h->restored) {
-        // no step was taken: still build the initial state and empty accumulators
-        for (auto &ph : h->probs) {
+    for (auto &ph : h->probs) {
+        if (h->steps_done == 0 && !h->restored) {
+            // no step was taken: still build the initial state and empty accumulators
             ppp_status s = launch_items(h, ph, 0, 0, st, nullptr, -1, ph.first_item, ph.n_items);
             if (s != PPP_OK) return s;
+        }
+        if (ph.dev.sequential) {
+            // windows the run has not entered yet get their (empty) accumulators
+            for (int64_t w = 1; w < ph.dev.n_windows; ++w) {
+                const int64_t at = w * ph.dev.n_steps;
+                if (at < h->steps_done) continue;
+                ppp_status s = launch_items(h, ph, at, at, st, nullptr, -1, ph.first_item, ph.n_items);
+                if (s != PPP_OK) return s;
+            }
         }
     }
     HIPCHK(h, hipEventRecord(h->ev[2], st));
@@ -575,6 +613,7 @@ ppp_status ppp_batch_create(const ppp_problem *ps, int32_t n, const char *tune_t
         std::string msg;
         ppp_status s = build_problem(&ps[i], h->probs[i], tune, msg);
         if (s == PPP_OK && ps[i].model != PPP_MODEL_CHAIN) { s = PPP_E_UNSUPPORTED; msg = "batched runs take chain problems"; }
+        if (s == PPP_OK && (ps[i].flags & PPP_FLAG_SEQUENTIAL)) { s = PPP_E_UNSUPPORTED; msg = "batched runs use the parallel protocol"; }
         if (s != PPP_OK) { g_create_err = "problem " + std::to_string(i) + ": " + msg; delete h; return s; }
     }
     // group problems by kernel shape; inside a group order items longest first
@@ -745,7 +784,9 @@ ppp_status ppp_get_timings(const ppp_handle *hc, ppp_timings *out) {
     }
     out->total_ms = ev_ms(h->ev[0], h->ev[4]);
     int64_t rs = 0;
-    for (auto &ph : h->probs) rs += (int64_t)ph.dev.n_windows * ph.dev.n_replicas * std::min(ph.dev.n_steps, h->steps_done);
+    for (auto &ph : h->probs)
+        rs += ph.dev.sequential ? (int64_t)ph.dev.n_replicas * std::min(total_steps(ph), h->steps_done)
+                                : (int64_t)ph.dev.n_windows * ph.dev.n_replicas * std::min(ph.dev.n_steps, h->steps_done);
     out->replica_steps = rs;
     out->sim_launches = h->sim_launches;
     out->variant_lanes = h->probs[0].G;
@@ -844,6 +885,7 @@ ppp_status ppp_trajectory(ppp_handle *h, void *ws, size_t bytes, int32_t window,
     if (!h) return PPP_E_INVALID_ARG;
     if (h->batch) return fail(h, PPP_E_UNSUPPORTED, "use a single-problem handle");
     const ProblemHost &ph = h->probs[0];
+    if (ph.dev.sequential) return fail(h, PPP_E_UNSUPPORTED, "trajectories are recorded for the parallel protocol");
     if (window < 0 || window >= ph.dev.n_windows || replica < 0 || replica >= ph.dev.n_replicas || !d_out)
         return fail(h, PPP_E_INVALID_ARG, "window/replica out of range");
     if (n_steps < 1 || n_steps > 100000 || n_steps > ph.dev.n_steps) return fail(h, PPP_E_INVALID_ARG, "n_steps out of range");

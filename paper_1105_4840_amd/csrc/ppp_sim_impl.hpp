@@ -34,6 +34,14 @@ __device__ __forceinline__ double centre_at(const DevProblem &P, double lam, int
     return P.xi_start + (lam - P.xi_start) * ((double)n / (double)P.n_pull);
 }
 
+// Sequential protocol: every replica runs the windows one after another,
+// n_steps each, with steps counted from the start of window 1.  A launch never
+// crosses a window boundary, so its window is that of its first step.  The
+// parallel protocol is the case of window 0 for every launch.
+__device__ __forceinline__ int64_t seq_window(const DevProblem &P, int64_t step_begin) {
+    return P.sequential ? step_begin / P.n_steps : 0;
+}
+
 // First step after `after` at which xi is sampled (steps n > n_equil with
 // n - n_equil a multiple of sample_every); the loops then count up to it
 // instead of taking a 64-bit remainder every step.
@@ -120,15 +128,19 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
                                                int64_t step_begin, int64_t step_end, double *traj, int traj_rep,
                                                unsigned int *lhist) {
     if ((int)threadIdx.x >= item.n_reps) return;
+    // record (window, replica); the sequential protocol keeps one state per replica
+    // and draws replica `rep`'s window-1 noise all the way
     const int64_t g = (int64_t)w * P.n_replicas + rep;
-    const uint32_t gid = (uint32_t)g;
+    const int64_t gs = P.sequential ? rep : g;
+    const uint32_t gid = (uint32_t)gs;
+    const int64_t s0 = P.sequential ? (int64_t)w * P.n_steps : 0;   // first step of this window
     const double *lam = reinterpret_cast<const double *>(ws + P.off_lambda);
     double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + g * A_NFIELDS;
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
-    T *st = state_ptr<T>(ws, P) + g * 2;
+    T *st = state_ptr<T>(ws, P) + gs * 2;
     const double lam_w = lam[w];
     const double x_start = reinterpret_cast<const double *>(ws + P.off_init)[0];
-    const int64_t n_end = step_end < P.n_steps ? step_end : P.n_steps;
+    const int64_t n_end = step_end < s0 + P.n_steps ? step_end : s0 + P.n_steps;
 
     double acc[A_NFIELDS];
     T x, eta_prev;
@@ -138,6 +150,12 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
         T z[4];
         Normal4<T>::get(P.seed, gid, 0u, 0u, 0u, z);
         eta_prev = z[0];
+    } else if (step_begin == s0) {
+        // sequential protocol entering window w: the state goes on, the record starts
+        // empty, and a replica frozen in the previous window stays frozen
+        acc_empty(acc);
+        acc[A_BLOWN] = acc_g[-(int64_t)P.n_replicas * A_NFIELDS + A_BLOWN];
+        x = st[0]; eta_prev = st[1];
     } else {
         for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
         x = st[0]; eta_prev = st[1];
@@ -150,9 +168,9 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
     bool alive = acc[A_BLOWN] == 0.0;
     T z[4];
     uint32_t zblock = 0xFFFFFFFFu;
-    int64_t n_sample = next_sample_after(P, step_begin);
+    int64_t n_sample = s0 + next_sample_after(P, step_begin - s0);
     for (int64_t n = step_begin + 1; n <= n_end && alive; ++n) {
-        const T F = force_1d<T>(P, x, (T)centre_at(P, lam_w, n - 1));
+        const T F = force_1d<T>(P, x, (T)(w == 0 || !P.sequential ? centre_at(P, lam_w, n - 1) : lam_w));
         const uint32_t blk = (uint32_t)(n >> 2);
         if (blk != zblock) { Normal4<T>::get(P.seed, gid, blk, 0u, 0u, z); zblock = blk; }
         const T eta = z[n & 3];
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ prob
     if (it >= n_items) return;
     const WorkItem item = items[it];
     const DevProblem &P = probs[item.prob];
-    const int w = item.window;
+    const int w = P.sequential ? (int)seq_window(P, step_begin) : item.window;
     const int rep = item.rep_begin + (int)threadIdx.x;
     unsigned int *lhist = P.xi_nbins <= lds_cap ? s_hist : nullptr;
     if (lhist) lhist_clear(lhist, P.xi_nbins);
@@ -424,18 +442,25 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     const bool active = lane_used && grp < item.n_reps;
     const int N = P.n_beads;
     const int64_t gfirst = (int64_t)item.window * P.n_replicas + item.rep_begin;
+    // gi: replica number (window * R + replica); the sequential protocol's items are
+    // window-1 replicas that run window `stage` in this launch
     const int64_t gi = gfirst + (active ? grp : 0);
-    const int w = (int)(gi / P.n_replicas);      // this replica's window
+    const int64_t stage = seq_window(P, step_begin);
+    const int64_t s0 = stage * P.n_steps;         // first step of this window (0: parallel protocol)
+    const int w = P.sequential ? (int)stage : (int)(gi / P.n_replicas);   // this replica's window now
+    const int64_t grec = P.sequential ? stage * P.n_replicas + gi : gi;   // its record
     const uint32_t gid = (uint32_t)gi;
     // the workgroup's histogram holds the windows item.window, item.window + 1, ...
-    unsigned int *lhist_w = lhist ? lhist + (int64_t)(w - item.window) * P.xi_nbins : nullptr;
+    // (the one window `stage` in the sequential protocol)
+    unsigned int *lhist_w = lhist ? lhist + (P.sequential ? 0 : (int64_t)(w - item.window) * P.xi_nbins) : nullptr;
     const double *lam = reinterpret_cast<const double *>(ws + P.off_lambda);
     const double *x0 = reinterpret_cast<const double *>(ws + P.off_init);
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
-    double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + gi * A_NFIELDS;
+    double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + grec * A_NFIELDS;
     T *st = state_ptr<T>(ws, P) + gi * 6 * NPAD;
     const double lam_w = lam[w];
-    const int64_t n_end = step_end < P.n_steps ? step_end : P.n_steps;
+    const int64_t n_end = step_end < s0 + P.n_steps ? step_end : s0 + P.n_steps;
+    auto centre = [&](int64_t n) { return stage == 0 ? centre_at(P, lam_w, n) : lam_w; };
     const int i0 = g * B;
     const int last = N - 1;
     const int owner = last / B;       // lane (within group) owning the pulled end
@@ -462,7 +487,16 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
             px[b] = st[0 * NPAD + i0 + b]; py[b] = st[1 * NPAD + i0 + b]; pz[b] = st[2 * NPAD + i0 + b];
             vx[b] = st[3 * NPAD + i0 + b]; vy[b] = st[4 * NPAD + i0 + b]; vz[b] = st[5 * NPAD + i0 + b];
         }
-        if (lane_used && g == owner) for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
+        if (lane_used && g == owner) {
+            if (step_begin == s0) {
+                // sequential protocol entering window `stage`: the record starts empty,
+                // and a replica frozen in the previous window stays frozen
+                acc_empty(acc);
+                acc[A_BLOWN] = acc_g[-(int64_t)P.n_replicas * A_NFIELDS + A_BLOWN];
+            } else {
+                for (int f = 0; f < A_NFIELDS; ++f) acc[f] = acc_g[f];
+            }
+        }
     }
     const bool record = traj != nullptr && gi == traj_rep && active;
     if (record && step_begin == 0) {
@@ -475,13 +509,13 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     const uint64_t bal0 = __ballot(blown0 != 0);
     bool alive = active && ((bal0 >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) == 0ull;
 
-    ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre_at(P, lam_w, step_begin), px, py, pz, fx, fy, fz, nullptr);
+    ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(step_begin), px, py, pz, fx, fy, fz, nullptr);
 
     const T h = (T)(0.5 * P.dt);
     const T c1 = (T)P.c1;
     const T hm = (T)(0.5 * P.dt * P.inv_mass);
     const T c2sd = (T)P.c2sd;
-    int64_t n_sample = next_sample_after(P, step_begin);
+    int64_t n_sample = s0 + next_sample_after(P, step_begin - s0);
     for (int64_t n = step_begin + 1; n <= n_end; ++n) {
         if (!alive) break;
 #pragma unroll
@@ -496,7 +530,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
             }
         }
-        ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre_at(P, lam_w, n), px, py, pz, fx, fy, fz, nullptr);
+        ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(n), px, py, pz, fx, fy, fz, nullptr);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = i0 + b;
@@ -561,7 +595,8 @@ __global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ p
     unsigned int *lhist = nk <= lds_cap ? s_hist : nullptr;
     if (lhist) lhist_clear(lhist, nk);
     run_chain_item<T, G, B>(P, item, ws, step_begin, step_end, traj, traj_rep, s_acc, lhist);
-    if (lhist) lhist_flush(lhist, nk, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + (int64_t)item.window * P.xi_nbins);
+    const int64_t w0 = P.sequential ? seq_window(P, step_begin) : item.window;
+    if (lhist) lhist_flush(lhist, nk, reinterpret_cast<unsigned long long *>(ws + P.off_hist) + w0 * P.xi_nbins);
 }
 
 // Persistent launch: workgroups take items from a queue (atomic ticket) until

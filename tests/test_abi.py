@@ -53,7 +53,9 @@ def _status(prob):
     lambda p: p.update(w_bin=0.0),
     lambda p: p.update(n_blocks=10 ** 6),
     lambda p: p.update(n_blocks=-1),
-    lambda p: p.update(flags=1),
+    lambda p: p.update(flags=2),
+    lambda p: p.update(flags=0x80000001),
+    lambda p: p.update(sequential=True, n_steps=2 ** 31, n_equil=0),   # 21 x 2^31 steps per replica
     lambda p: p.update({"lambda": [0.0]}),
     lambda p: p.update({"lambda": [0.0, 1.0, 1.0]}),
     lambda p: p.update({"lambda": [0.0, 1.0, 0.5]}),
@@ -92,6 +94,20 @@ def test_valid_problems_and_workspace_size():
     p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
     p["lambda"] = p["lambda"][::-1]
     assert _status(p) == 0
+
+
+def test_sequential_protocol_accepted_where_supported():
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    p["sequential"] = True
+    assert _status(p) == 0
+    h = ppp.ppp_create(p)
+    try:
+        # trajectories are recorded for the parallel protocol only
+        assert ppp.lib().ppp_trajectory(h, None, 0, 0, 0, 10, None, None) in (ppp.PPP_E_UNSUPPORTED, ppp.PPP_E_INVALID_ARG)
+    finally:
+        ppp.ppp_destroy(h)
+    with pytest.raises(ppp.PppError):
+        ppp.ppp_batch_create([p, dict(p)])
 
 
 def test_error_strings():

@@ -240,6 +240,70 @@ def test_run_without_samples():
         assert not np.any(np.isfinite(res[key][1:])) and not np.any(np.isfinite(ref[key][1:])), key
 
 
+SEQ_CASES = [
+    ("1d", None, dict(n_replicas=70, n_steps=800, n_windows=6)),
+    ("1d-pull", None, dict(n_replicas=40, n_steps=600, n_windows=4)),
+    ("chain10", 10, dict(n_replicas=70, n_steps=300, n_windows=4)),
+    ("chain37", 37, dict(n_replicas=20, n_steps=200, n_windows=3)),
+    ("chain100", 100, dict(n_replicas=12, n_steps=150, n_windows=3)),
+]
+
+
+@pytest.mark.parametrize("case", SEQ_CASES, ids=[c[0] for c in SEQ_CASES])
+def test_sequential_run_parity_fp64(case):
+    """Sequential pulling protocol (each replica runs the windows one after
+    another) against the oracle, element by element."""
+    name, n_beads, kw = case
+    _say(f"case sequential {name}")
+    if n_beads is None:
+        prob = ppp_inputs.config_1d(precision="fp64", **kw)
+        if name.endswith("pull"):
+            prob["n_pull"] = 200
+    else:
+        prob = ppp_inputs.config_chain_small(n_beads, precision="fp64", **kw)
+        prob["w_bin"] = 0.05
+    prob["w_half_bins"] = 2000
+    prob["sequential"] = True
+    res, tim = ppp.run(prob)
+    assert tim["replica_steps"] == prob["n_replicas"] * len(prob["lambda"]) * prob["n_steps"]
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+
+
+def test_sequential_uneven_chunks_and_frozen_replicas():
+    _say("case sequential chunks")
+    prob = ppp_inputs.config_chain_small(10, n_replicas=30, n_steps=90, n_windows=4, precision="fp64")
+    prob["sequential"] = True
+    full, _ = ppp.run(prob)
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        ppp.ppp_begin(h, ws)
+        for n in [7, 83, 1, 90, 13, 45, 2]:          # stops inside windows and on their boundaries
+            ppp.ppp_advance(h, n)
+        ppp.ppp_finalize(h)                          # the last window never entered: empty records
+        part = ppp.ppp_get_result(h, prob)
+        assert ppp.ppp_steps_done(h) == 241
+        ppp.ppp_begin(h, ws)
+        ppp.ppp_advance(h, 10 ** 9)
+        ppp.ppp_finalize(h)
+        again = ppp.ppp_get_result(h, prob)
+    finally:
+        ppp.ppp_destroy(h)
+    for key in ("dF_je", "xi_mean", "xi_hist", "n_samples"):
+        assert np.array_equal(full[key], again[key]), key
+    # 241 steps: windows 1 and 2 complete, window 3 up to step 61 of 90, window 4 empty
+    assert np.array_equal(part["n_samples"][:2], full["n_samples"][:2])
+    assert 0 < part["n_samples"][2] < full["n_samples"][2] and part["n_samples"][3] == 0
+    # a replica that blows up stays frozen in the later windows
+    init = ppp_inputs.random_chain_coords(10, 1, seed=4)[0]
+    init[5, 1] = np.nan
+    prob2 = dict(prob, init_coords=init.ravel().tolist())
+    res, _ = ppp.run(prob2)
+    assert np.all(res["n_blown_up"] == prob["n_replicas"]) and np.all(res["n_samples"] == 0)
+
+
 def test_checkpoint_resume_is_bit_identical():
     _say("case checkpoint")
     prob = ppp_inputs.config_chain_small(13, n_replicas=40, n_steps=800, n_windows=4, precision="fp64")

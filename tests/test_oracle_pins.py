@@ -427,3 +427,47 @@ def test_reach_criterion_hand_case():
     p2, xi2, kept2 = _synthetic(smp[::-1], lam[::-1], 10.0, 1.0, blocks=2)
     r2 = estimators.estimate(p2, xi2, kept2, with_appc=False)
     assert np.allclose(r2["reach"], [3.0 - 2.0, 1.0 - 0.0])
+
+
+# --------------------------------------------------------------------------- sequential protocol (Sec. III(i))
+
+
+def test_sequential_first_window_repeats_parallel_protocol():
+    """Window 1 of the sequential protocol is the parallel protocol's window 1:
+    same start, same restraint, same noise counters."""
+    for p in (ppp_inputs.config_1d(n_replicas=12, n_steps=1500, n_windows=4),
+              ppp_inputs.config_chain_small(7, n_replicas=6, n_steps=400, n_windows=3)):
+        xi, kept, _ = oracle.run(p)
+        xs, ks, _ = oracle.run(dict(p, sequential=True))
+        R = p["n_replicas"]
+        assert np.array_equal(xi[:R], xs[:R]) and np.array_equal(kept[:R], ks[:R])
+        assert not np.array_equal(xi[R:], xs[R:])      # later windows start from the previous one
+
+
+def test_sequential_harmonic_closed_form():
+    p = dict(ppp_inputs.config_harmonic_1d(n_replicas=128, n_steps=6000), sequential=True)
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    Fc, mu, var = quadrature.harmonic_closed_form(p["pot_kappa"], p["k"], p["kT"], p["lambda"])
+    z = (r["dF_je"][-1] - (Fc[-1] - Fc[0])) / r["dF_je_se"][-1]
+    assert abs(z) < 3.5, z
+
+
+def test_sequential_double_well_quadrature():
+    p = dict(ppp_inputs.config_1d(n_replicas=128, n_steps=10000, seed=4), sequential=True)
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    F, mu, var = quadrature.restrained_1d(quadrature.double_well(), p["lambda"], p["k"], p["kT"])
+    z = (r["dF_je"] - (F - F[0]))[1:] / r["dF_je_se"][1:]
+    assert abs(z[-1]) < 3.5 and np.max(np.abs(z)) < 4.0, z
+
+
+def test_sequential_frozen_replica_stays_frozen():
+    p = dict(ppp_inputs.config_chain_small(5, n_replicas=3, n_steps=100, n_windows=3), sequential=True)
+    init = ppp_inputs.random_chain_coords(5, 1, seed=2)[0]
+    init[2, 0] = np.nan
+    p["init_coords"] = init.ravel().tolist()
+    xi, kept, _ = oracle.run(p)
+    assert np.all(kept == 0)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    assert np.all(r["n_blown_up"] == 3)
