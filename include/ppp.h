@@ -151,6 +151,13 @@ typedef struct {
     double *dlambda_over_sigma;        /* |dlambda_i| / sigma_i */
     double *dlambda_over_reach;        /* |dlambda_i| / (end of rho_i in the pulling direction - <x_i>) */
     int32_t *criterion_ok;             /* |dlambda_i| <= that reach (Sec. IV B) */
+    /* [s] the paper's formulas as printed, beside the readings above */
+    double *dF_fluct_literal;          /* Eq. 14 with (lambda_j - lambda_1)/j in place of every
+                                          increment up to lambda_j (j counted from 1) */
+    double *dF_gauss_literal;          /* Eq. 13 likewise */
+    double *dF_je_hist_literal;        /* App. C as printed: x at the bin's upper edge, work bin
+                                          [W/dW] by truncation toward zero, Omega_j(0) replaced by
+                                          the mean of its neighbours (j >= 2) */
     /* histograms */
     uint64_t *xi_hist;                 /* [s*K] */
     uint64_t *xi_under_over;           /* [s*2] */

@@ -91,6 +91,47 @@ def work_distributions(prob, hist, n):
             "sigma_w": sigma_w, "q_bins": q_bins, "dF_je_var_paper": var_paper}
 
 
+def work_distributions_literal(prob, hist, n):
+    """App. C as printed: the x representative of bin b is x = (b+1) dxi past
+    xi_min (x = j dx with j counted from 1), the work W = w dW + dW_{j-1}(x) of
+    a pair goes to bin [W / dW] taken as C's conversion to an integer
+    (truncation toward zero), and each Omega_j (j >= 2) has its bin at W = 0
+    replaced by the mean of its two neighbours, the smoothing the paper applies
+    to the spike that this rounding makes there.  Contributions are
+    accumulated (+=).  Returns the Omega_j and dF^JE from their normalised
+    exponential averages with W at w dW."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    s = len(lam)
+    k = float(prob["k"]); kT = float(prob["kT"]); beta = 1.0 / kT
+    M = int(prob["w_half_bins"]); dWb = float(prob["w_bin"])
+    K = int(prob["xi_nbins"]); x0 = float(prob["xi_min"]); dx = float(prob["xi_bin"])
+    nb = 2 * M + 1
+    wv = np.arange(-M, M + 1, dtype=np.float64)
+    omega = np.zeros((s, nb))
+    omega[0, M] = 1.0
+    xb = x0 + (np.arange(K) + 1.0) * dx
+    for j in range(1, s):
+        rho = hist[j - 1] / max(int(n[j - 1]), 1)
+        f = 0.5 * k * ((xb - lam[j]) ** 2 - (xb - lam[j - 1]) ** 2) / dWb   # dW in bins
+        prev = omega[j - 1]
+        cur = omega[j]
+        for b in np.nonzero(rho)[0]:
+            # trunc(w + f) is w + floor(f) where w + f >= 0 and w + ceil(f) where w + f < 0:
+            # two runs of source bins, each moved by one integer shift
+            first_up = int(np.ceil(-f[b]))            # smallest w with w + f >= 0
+            for w_lo, w_hi, sh in ((first_up, M, int(np.floor(f[b]))), (-M, first_up - 1, int(np.ceil(f[b])))):
+                lo, hi = max(w_lo, -M, -M - sh), min(w_hi, M, M - sh)
+                if lo <= hi:
+                    cur[lo + sh + M:hi + sh + M + 1] += rho[b] * prev[lo + M:hi + M + 1]
+        cur[M] = 0.5 * (cur[M - 1] + cur[M + 1])
+    je = np.full(s, np.nan)
+    for j in range(s):
+        tot = omega[j].sum()
+        if tot > 0:
+            je[j] = -kT * np.log(np.sum(omega[j] * np.exp(-beta * wv * dWb)) / tot)
+    return {"work_hist_literal": omega, "dF_je_hist_literal": je}
+
+
 def product_form(prob, hist, n):
     """The exact exponential average of the binned x distributions, without work binning:
     -kT sum_{i<j} ln sum_b rho_i(b) exp(-beta dW_i(x_b)).  Used to pin the recursion."""

@@ -94,7 +94,18 @@ def profiles(stats, lam, k, kT):
         rev[j] = rev[j - 1] + kT * (sj["lse_rev"] - np.log(sj["n"]))
     com = 0.5 * (je + fl)
     unc = 0.5 * (je - fl)
-    return {"dF_je": je, "dF_fluct": fl, "dF_gauss": g, "dF_com": com, "dF_unc": unc, "dF_rev": rev}
+    # Eqs. 14 and 13 as printed, with lambda_j as the end point: the increment
+    # (lambda_j - lambda_1)/j in place of each step (j counted from 1)
+    fl_lit = np.zeros(s); g_lit = np.zeros(s)
+    for j in range(1, s):
+        n_pts = j + 1
+        span = lam[j] - lam[0]
+        s1 = sum(lam[i] - stats[i]["mean"] for i in range(j))
+        s2 = sum(1.0 - k * stats[i]["var"] / kT for i in range(j))
+        fl_lit[j] = k * span * s1 / n_pts
+        g_lit[j] = k * span ** 2 / (2.0 * n_pts) * s2 / n_pts + fl_lit[j]
+    return {"dF_je": je, "dF_fluct": fl, "dF_gauss": g, "dF_com": com, "dF_unc": unc, "dF_rev": rev,
+            "dF_fluct_literal": fl_lit, "dF_gauss_literal": g_lit}
 
 
 def histograms(xi, kept, prob):
@@ -179,4 +190,5 @@ def estimate(prob, xi, kept, with_appc=True):
 
     if with_appc and int(prob.get("w_half_bins", 0)) > 0:
         res.update(appc.work_distributions(prob, hist, n))
+        res.update(appc.work_distributions_literal(prob, hist, n))
     return res

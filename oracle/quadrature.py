@@ -110,3 +110,15 @@ def estimator_expectations(lam, mu, var, k, kT):
         fl[j] = fl[j - 1] + k * dl * (lam[i] - mu[i])
         g[j] = g[j - 1] + k * dl * (lam[i] - mu[i]) + 0.5 * k * dl * dl * (1.0 - k * var[i] / kT)
     return fl, g
+
+
+def estimator_expectations_literal(lam, mu, var, k, kT):
+    """The same for Eqs. 14 and 13 as printed: (lambda_j - lambda_1)/j per step up to lambda_j."""
+    lam = np.asarray(lam, dtype=np.float64)
+    s = len(lam)
+    fl = np.zeros(s); g = np.zeros(s)
+    for j in range(1, s):
+        span = lam[j] - lam[0]
+        fl[j] = k * span * np.sum(lam[:j] - mu[:j]) / (j + 1)
+        g[j] = k * span ** 2 / (2.0 * (j + 1)) * np.sum(1.0 - k * np.asarray(var[:j]) / kT) / (j + 1) + fl[j]
+    return fl, g

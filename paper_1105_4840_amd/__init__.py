@@ -62,12 +62,13 @@ _RESULT_S_I64 = ["q_bins"]
 _RESULT_S2 = ["work_lost", "xi_mean", "xi_std", "gamma2", "xi_min_sample", "xi_max_sample", "lse_fwd", "lse_rev"]
 _RESULT_S_I64_2 = ["n_samples", "n_blown_up"]
 _RESULT_P = ["kish_frac", "overlap_ovl", "dlambda_over_sigma", "dlambda_over_reach"]
+_RESULT_LIT = ["dF_fluct_literal", "dF_gauss_literal", "dF_je_hist_literal"]
 
 
 class ppp_result(ctypes.Structure):
     _fields_ = ([(n, _dp) for n in _RESULT_S] + [(n, _i64p) for n in _RESULT_S_I64] +
                 [(n, _dp) for n in _RESULT_S2] + [(n, _i64p) for n in _RESULT_S_I64_2] +
-                [(n, _dp) for n in _RESULT_P] + [("criterion_ok", _i32p)] +
+                [(n, _dp) for n in _RESULT_P] + [("criterion_ok", _i32p)] + [(n, _dp) for n in _RESULT_LIT] +
                 [("xi_hist", _u64p), ("xi_under_over", _u64p), ("work_hist", _dp)])
 
 
@@ -257,7 +258,7 @@ def _result_buffers(prob):
     s = len(prob["lambda"]); K = int(prob["xi_nbins"]); M = int(prob.get("w_half_bins", 0))
     bufs = {}
     r = ppp_result()
-    for n in _RESULT_S + _RESULT_S2:
+    for n in _RESULT_S + _RESULT_S2 + _RESULT_LIT:
         bufs[n] = np.full(s, np.nan); setattr(r, n, bufs[n].ctypes.data_as(_dp))
     for n in _RESULT_S_I64 + _RESULT_S_I64_2:
         bufs[n] = np.zeros(s, dtype=np.int64); setattr(r, n, bufs[n].ctypes.data_as(_i64p))

@@ -30,6 +30,7 @@ enum OutField : int {
     O_XI_MEAN, O_XI_STD, O_GAMMA2, O_XI_MINS, O_XI_MAXS, O_LSE_FWD, O_LSE_REV,
     O_N_SAMPLES, O_N_BLOWN, O_UNDER, O_OVER,
     O_KISH, O_OVL, O_DL_SIGMA, O_DL_REACH, O_CRIT,
+    O_DF_FLUCT_LIT, O_DF_GAUSS_LIT, O_DF_JE_HIST_LIT,
     O_NFIELDS
 };
 
@@ -69,10 +70,12 @@ struct DevProblem {
     int64_t off_tot;        // double [s][A_NFIELDS]
     int64_t off_jack;       // double [B][JK_FIELDS][s]
     int64_t off_out;        // double [O_NFIELDS][s]
-    int64_t off_pairs_shift;// int32 [s][K]
-    int64_t off_pairs_prob; // double [s][K]
-    int64_t off_npairs;     // int32 [s]
-    int64_t off_omega;      // double [s][2M+1]
+    // App. C in two chains: 0 the primary reading, 1 the paper's listing as printed
+    int64_t off_pairs_shift;// int32 [2][s][K] (chain 1: floor of the work in bins)
+    int64_t off_pairs_ceil; // int32 [s][K] (chain 1: its ceiling)
+    int64_t off_pairs_prob; // double [2][s][K]
+    int64_t off_npairs;     // int32 [2][s]
+    int64_t off_omega;      // double [2][s][2M+1]
 };
 
 // n_reps consecutive replicas of one problem, starting at replica rep_begin of

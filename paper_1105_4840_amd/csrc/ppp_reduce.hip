@@ -32,7 +32,8 @@ __global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ 
         double *om = dptr(ws, P.off_omega);
         const int64_t nb = 2 * (int64_t)P.w_half_bins + 1;
         const int64_t no = (int64_t)P.n_windows * nb;
-        for (int64_t i = tid; i < no; i += stride) om[i] = (i == P.w_half_bins) ? 1.0 : 0.0;  // Omega_1: W = 0
+        for (int64_t i = tid; i < 2 * no; i += stride)     // both chains; Omega_1: W = 0
+            om[i] = (i % no == P.w_half_bins) ? 1.0 : 0.0;
     }
     if (blockIdx.y == 0 && tid < n_tickets) tickets[tid] = 0;
 }
@@ -40,7 +41,7 @@ __global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ 
 hipError_t launch_init(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_k, int max_m,
                        int *d_tickets, int n_tickets, hipStream_t stream) {
     int64_t work = (int64_t)max_windows * max_k;
-    const int64_t wo = (int64_t)max_windows * (2 * (int64_t)max_m + 1);
+    const int64_t wo = 2 * (int64_t)max_windows * (2 * (int64_t)max_m + 1);
     if (wo > work) work = wo;
     int nb = (int)((work + 255) / 256);
     if (nb < 1) nb = 1;
@@ -171,12 +172,21 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
     // (c) profiles: prefix sums over the steps
     if (t == 0) {
         double je = 0, fl = 0, ga = 0, rev = 0;
+        double s1 = 0, s2 = 0;   // sums over i < j of (lambda_i - <x_i>) and (1 - gamma_i^2)
         OUT(O_DF_JE, 0) = 0; OUT(O_DF_FLUCT, 0) = 0; OUT(O_DF_GAUSS, 0) = 0; OUT(O_DF_REV, 0) = 0;
+        OUT(O_DF_FLUCT_LIT, 0) = 0; OUT(O_DF_GAUSS_LIT, 0) = 0;
         for (int j = 1; j < s; ++j) {
             const WinStat st = win_stat(tot + (int64_t)(j - 1) * A_NFIELDS, lam[j - 1]);
             double dje, dfl, dga;
             step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
             je += dje; fl += dfl; ga += dga;
+            // Eqs. 14 and 13 as printed, lambda_j taken as the end point of j + 1 windows
+            s1 += lam[j - 1] - st.mean;
+            s2 += 1.0 - P.k * st.var / P.kT;
+            const double span = lam[j] - lam[0], npts = (double)(j + 1);
+            const double fl_lit = P.k * span * s1 / npts;
+            OUT(O_DF_FLUCT_LIT, j) = fl_lit;
+            OUT(O_DF_GAUSS_LIT, j) = P.k * span * span / (2.0 * npts) * s2 / npts + fl_lit;
             const WinStat sj = win_stat(tot + (int64_t)j * A_NFIELDS, lam[j]);
             rev += P.kT * (sj.lse_r - log(sj.n));
             OUT(O_DF_JE, j) = je; OUT(O_DF_FLUCT, j) = fl; OUT(O_DF_GAUSS, j) = ga; OUT(O_DF_REV, j) = rev;
@@ -250,7 +260,37 @@ __global__ void k_appc_pairs(const DevProblem *__restrict__ probs, char *__restr
 #pragma clang fp contract(off)
     const DevProblem &P = probs[blockIdx.y];
     const int i = blockIdx.x;
-    if (P.w_half_bins <= 0 || i + 1 >= P.n_windows || threadIdx.x != 0) return;
+    if (P.w_half_bins <= 0 || i + 1 >= P.n_windows || threadIdx.x > 1) return;
+    if (threadIdx.x == 1) {
+        // chain 1, the listing as printed: x at the bin's upper edge; the pair's work
+        // W = w dW + dW_i(x) goes to bin trunc(W / dW), i.e. w + floor(f) where
+        // w + f >= 0 and w + ceil(f) below, f = dW_i(x) / dW
+        const int K = P.xi_nbins;
+        const double *lam = dptr(ws, P.off_lambda);
+        const double *tot = dptr(ws, P.off_tot);
+        const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)i * K;
+        const int64_t sK = (int64_t)P.n_windows * K;
+        int *fl = reinterpret_cast<int *>(ws + P.off_pairs_shift) + sK + (int64_t)i * K;
+        int *ce = reinterpret_cast<int *>(ws + P.off_pairs_ceil) + (int64_t)i * K;
+        double *prob = dptr(ws, P.off_pairs_prob) + sK + (int64_t)i * K;
+        const double n = tot[(int64_t)i * A_NFIELDS + A_N];
+        const double li = lam[i], lj = lam[i + 1];
+        int np = 0;
+        for (int b = 0; b < K; ++b) {
+            const unsigned long long c = hist[b];
+            if (c == 0ull) continue;
+            const double xb = P.xi_min + ((double)b + 1.0) * P.xi_bin;
+            const double f = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li)) / P.w_bin;
+            const double ff = floor(f), fc = ceil(f);
+            const int sf = ff > 2.0e9 ? 2000000000 : (ff < -2.0e9 ? -2000000000 : (int)ff);
+            const int sc = fc > 2.0e9 ? 2000000000 : (fc < -2.0e9 ? -2000000000 : (int)fc);
+            const double pb = (double)c / n;
+            if (np > 0 && fl[np - 1] == sf && ce[np - 1] == sc) prob[np - 1] += pb;
+            else { fl[np] = sf; ce[np] = sc; prob[np] = pb; ++np; }
+        }
+        reinterpret_cast<int *>(ws + P.off_npairs)[P.n_windows + i] = np;
+        return;
+    }
     const int K = P.xi_nbins;
     const double *lam = dptr(ws, P.off_lambda);
     const double *tot = dptr(ws, P.off_tot);
@@ -275,32 +315,66 @@ __global__ void k_appc_pairs(const DevProblem *__restrict__ probs, char *__restr
 }
 
 // Omega_j(w) = sum_t prob_t Omega_{j-1}(w - shift_t), the folding step of App. C.
+// Chain 1 (blockIdx.z) folds as printed: target w > 0 takes source w - floor(f),
+// w < 0 takes w - ceil(f), and w = 0 both (the spike of truncation), and its
+// Omega_j(0) is then replaced by the mean of Omega_j(-1) and Omega_j(1).
 __global__ __launch_bounds__(256) void k_appc_step(const DevProblem *__restrict__ probs, char *__restrict__ ws, int j) {
     const DevProblem &P = probs[blockIdx.y];
     if (P.w_half_bins <= 0 || j >= P.n_windows) return;
-    const int64_t nb = 2 * (int64_t)P.w_half_bins + 1;
+    const int chain = blockIdx.z;
+    const int M = P.w_half_bins;
+    const int64_t nb = 2 * (int64_t)M + 1;
+    const int64_t sK = (int64_t)P.n_windows * P.xi_nbins;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int np = reinterpret_cast<const int *>(ws + P.off_npairs)[j - 1];
-    const int *shift = reinterpret_cast<const int *>(ws + P.off_pairs_shift) + (int64_t)(j - 1) * P.xi_nbins;
-    const double *prob = dptr(ws, P.off_pairs_prob) + (int64_t)(j - 1) * P.xi_nbins;
-    const double *prev = dptr(ws, P.off_omega) + (int64_t)(j - 1) * nb;
-    double *cur = dptr(ws, P.off_omega) + (int64_t)j * nb;
+    const int np = reinterpret_cast<const int *>(ws + P.off_npairs)[chain * P.n_windows + j - 1];
+    const int *shift = reinterpret_cast<const int *>(ws + P.off_pairs_shift) + chain * sK + (int64_t)(j - 1) * P.xi_nbins;
+    const int *ceil_s = reinterpret_cast<const int *>(ws + P.off_pairs_ceil) + (int64_t)(j - 1) * P.xi_nbins;
+    const double *prob = dptr(ws, P.off_pairs_prob) + chain * sK + (int64_t)(j - 1) * P.xi_nbins;
+    const double *prev = dptr(ws, P.off_omega) + chain * (int64_t)P.n_windows * nb + (int64_t)(j - 1) * nb;
+    double *cur = dptr(ws, P.off_omega) + chain * (int64_t)P.n_windows * nb + (int64_t)j * nb;
     __shared__ int s_shift[256];
+    __shared__ int s_ceil[256];
     __shared__ double s_prob[256];
-    double acc = 0.0;
+    const int64_t wv = w - M;                 // work bin of this thread
+    double acc = 0.0, acc_m = 0.0, acc_p = 0.0;   // chain 1 at W = 0 also needs bins -1 and +1
     for (int t0 = 0; t0 < np; t0 += 256) {
         const int cnt = np - t0 < 256 ? np - t0 : 256;
         __syncthreads();
-        if ((int)threadIdx.x < cnt) { s_shift[threadIdx.x] = shift[t0 + threadIdx.x]; s_prob[threadIdx.x] = prob[t0 + threadIdx.x]; }
+        if ((int)threadIdx.x < cnt) {
+            s_shift[threadIdx.x] = shift[t0 + threadIdx.x];
+            s_ceil[threadIdx.x] = chain ? ceil_s[t0 + threadIdx.x] : 0;
+            s_prob[threadIdx.x] = prob[t0 + threadIdx.x];
+        }
         __syncthreads();
         if (w < nb) {
-            for (int t = 0; t < cnt; ++t) {
-                const int64_t src = w - s_shift[t];
-                if (src >= 0 && src < nb) acc += s_prob[t] * prev[src];
+            if (chain == 0) {
+                for (int t = 0; t < cnt; ++t) {
+                    const int64_t src = w - s_shift[t];
+                    if (src >= 0 && src < nb) acc += s_prob[t] * prev[src];
+                }
+            } else {
+                for (int t = 0; t < cnt; ++t) {
+                    const int sf = s_shift[t], sc = s_ceil[t];
+                    const double pt = s_prob[t];
+                    if (wv > 0) {
+                        const int64_t src = w - sf;
+                        if (src >= 0 && src < nb) acc += pt * prev[src];
+                    } else if (wv < 0) {
+                        const int64_t src = w - sc;
+                        if (src >= 0 && src < nb) acc += pt * prev[src];
+                    } else {
+                        const int64_t s1 = M - (int64_t)sf, s2 = M - (int64_t)sc;
+                        if (s1 >= 0 && s1 < nb) acc += pt * prev[s1];
+                        if (sc != sf && s2 >= 0 && s2 < nb) acc += pt * prev[s2];
+                        const int64_t sm = M - 1 - (int64_t)sc, sp = M + 1 - (int64_t)sf;   // bins -1 and +1
+                        if (sm >= 0 && sm < nb) acc_m += pt * prev[sm];
+                        if (sp >= 0 && sp < nb) acc_p += pt * prev[sp];
+                    }
+                }
             }
         }
     }
-    if (w < nb) cur[w] = acc;
+    if (w < nb) cur[w] = (chain == 1 && wv == 0) ? 0.5 * (acc_m + acc_p) : acc;
 }
 
 // Statistics of Omega_j: normalised exponential average (App. B.5), spread and
@@ -308,12 +382,13 @@ __global__ __launch_bounds__(256) void k_appc_step(const DevProblem *__restrict_
 __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
     const DevProblem &P = probs[blockIdx.y];
     const int j = blockIdx.x;
+    const int chain = blockIdx.z;
     __shared__ double sh[256];
     const int s = P.n_windows;
     if (P.w_half_bins <= 0 || j >= s) return;
     const int M = P.w_half_bins;
     const int64_t nb = 2 * (int64_t)M + 1;
-    const double *om = dptr(ws, P.off_omega) + (int64_t)j * nb;
+    const double *om = dptr(ws, P.off_omega) + chain * (int64_t)s * nb + (int64_t)j * nb;
     double *out = dptr(ws, P.off_out);
     const double beta = P.beta, dWb = P.w_bin;
     const double shift_mid = 0.5 * (double)j * dWb;
@@ -352,7 +427,9 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
     sl = block_sum(sl, sh);
     sm = block_sum(sm, sh);
     vv = block_sum(vv, sh);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && chain == 1) {
+        out[(int64_t)O_DF_JE_HIST_LIT * s + j] = tot > 0 ? -P.kT * (emax + log(sl / tot)) : NAN;
+    } else if (threadIdx.x == 0) {
         const double kT = P.kT;
         const double sig = sqrt(fmax(vv / tot, 0.0));
         out[(int64_t)O_DF_JE_HIST * s + j] = tot > 0 ? -kT * (emax + log(sl / tot)) : NAN;
@@ -373,8 +450,8 @@ hipError_t launch_appc(const DevProblem *d_probs, int n_probs, char *ws, int max
     const int64_t nb = 2 * (int64_t)max_m + 1;
     const int grid = (int)((nb + 255) / 256);
     for (int j = 1; j < max_windows; ++j)
-        hipLaunchKernelGGL(k_appc_step, dim3(grid, n_probs), dim3(256), 0, stream, d_probs, ws, j);
-    hipLaunchKernelGGL(k_appc_stats, dim3(max_windows, n_probs), dim3(256), 0, stream, d_probs, ws);
+        hipLaunchKernelGGL(k_appc_step, dim3(grid, n_probs, 2), dim3(256), 0, stream, d_probs, ws, j);
+    hipLaunchKernelGGL(k_appc_stats, dim3(max_windows, n_probs, 2), dim3(256), 0, stream, d_probs, ws);
     return hipGetLastError();
 }
 

@@ -304,10 +304,11 @@ int64_t layout_problem(ProblemHost &ph, int64_t at) {
     d.off_jack = take(Bk * JK_FIELDS * s * 8);
     d.off_out = take((int64_t)O_NFIELDS * s * 8);
     if (d.w_half_bins > 0) {
-        d.off_pairs_shift = take(s * K * 4);
-        d.off_pairs_prob = take(s * K * 8);
-        d.off_npairs = take(s * 4);
-        d.off_omega = take(s * (2 * (int64_t)d.w_half_bins + 1) * 8);
+        d.off_pairs_shift = take(2 * s * K * 4);
+        d.off_pairs_ceil = take(s * K * 4);
+        d.off_pairs_prob = take(2 * s * K * 8);
+        d.off_npairs = take(2 * s * 4);
+        d.off_omega = take(2 * s * (2 * (int64_t)d.w_half_bins + 1) * 8);
     }
     ph.region_end = at;
     return at;
@@ -451,6 +452,8 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
     put(out->dF_com_se, o, F(O_DF_COM_SE), s);
     put(out->dF_unc, o, F(O_DF_UNC), s);
     put(out->dF_rev, o, F(O_DF_REV), s);
+    put(out->dF_fluct_literal, o, F(O_DF_FLUCT_LIT), s);
+    put(out->dF_gauss_literal, o, F(O_DF_GAUSS_LIT), s);
     const bool appc = d.w_half_bins > 0;
     if (appc) {
         put(out->dF_je_hist, o, F(O_DF_JE_HIST), s);
@@ -459,8 +462,10 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
         put(out->sigma_w, o, F(O_SIGMA_W), s);
         put_i64(out->q_bins, o, F(O_Q_BINS), s);
         put(out->work_lost, o, F(O_WORK_LOST), s);
+        put(out->dF_je_hist_literal, o, F(O_DF_JE_HIST_LIT), s);
     } else {
-        for (double *p : {out->dF_je_hist, out->dF_je_hist_mid, out->dF_je_var_paper, out->sigma_w, out->work_lost})
+        for (double *p : {out->dF_je_hist, out->dF_je_hist_mid, out->dF_je_var_paper, out->sigma_w, out->work_lost,
+                          out->dF_je_hist_literal})
             if (p) for (int64_t i = 0; i < s; ++i) p[i] = NAN;
         if (out->q_bins) for (int64_t i = 0; i < s; ++i) out->q_bins[i] = 0;
     }

@@ -141,7 +141,7 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
     s = len(prob["lambda"])
     assert np.allclose(res["lse_fwd"][:s - 1], ref["lse_fwd"][:s - 1], rtol=1e-11, atol=1e-9)
     assert np.allclose(res["lse_rev"][1:], ref["lse_rev"][1:], rtol=1e-11, atol=1e-9)
-    for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com", "dF_unc", "dF_rev"):
+    for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com", "dF_unc", "dF_rev", "dF_fluct_literal", "dF_gauss_literal"):
         assert np.max(np.abs(res[key] - ref[key])) < prof_tol * (1 + np.max(np.abs(ref[key]))), key
     for key in ("dF_je_se", "dF_fluct_se", "dF_gauss_se", "dF_com_se"):
         assert np.allclose(res[key][1:], ref[key][1:], rtol=1e-7, atol=1e-12, equal_nan=True), key
@@ -150,7 +150,7 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
     assert np.array_equal(res["criterion_ok"].astype(bool), ref["criterion_ok"][:s - 1])
     if int(prob.get("w_half_bins", 0)) > 0:
         assert np.max(np.abs(res["work_hist"] - ref["work_hist"])) < 1e-12
-        for key in ("dF_je_hist", "dF_je_hist_mid"):
+        for key in ("dF_je_hist", "dF_je_hist_mid", "dF_je_hist_literal"):
             assert np.allclose(res[key], ref[key], rtol=1e-9, atol=1e-8, equal_nan=True), key
         assert np.array_equal(res["q_bins"], ref["q_bins"])
         assert np.allclose(res["sigma_w"], ref["sigma_w"], rtol=1e-9, atol=1e-12)

@@ -471,3 +471,70 @@ def test_sequential_frozen_replica_stays_frozen():
     assert np.all(kept == 0)
     r = estimators.estimate(p, xi, kept, with_appc=False)
     assert np.all(r["n_blown_up"] == 3)
+
+
+# --------------------------------------------------------------------------- paper-literal readings
+
+
+def test_literal_eq14_on_uniform_windows_and_double_well_value():
+    """With uniform windows, (lambda_j - lambda_1)/j (j counted from 1 at lambda_1,
+    i.e. j+1 points up to index j) replaces the increment dl by j dl/(j+1), so
+    Eq. 14 as printed is the increment form times j/(j+1).  On the double well
+    with exact moments it gives -1.9125 kT at lambda = 1.5 (against -2.0081 for
+    the increment form and exactly 0 for the free energy)."""
+    rng = np.random.default_rng(5)
+    lam = np.linspace(-1.0, 2.0, 13)
+    mu = lam + rng.normal(0, 0.2, lam.size); var = rng.uniform(0.01, 0.05, lam.size)
+    fl, g = quadrature.estimator_expectations(lam, mu, var, 30.0, 1.0)
+    fl_l, g_l = quadrature.estimator_expectations_literal(lam, mu, var, 30.0, 1.0)
+    j = np.arange(lam.size)
+    assert np.allclose(fl_l, fl * j / (j + 1), atol=1e-12)
+    p = ppp_inputs.config_1d()
+    F, mu, var = quadrature.restrained_1d(quadrature.double_well(), p["lambda"], p["k"], p["kT"])
+    fl, _ = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
+    fl_l, _ = quadrature.estimator_expectations_literal(p["lambda"], mu, var, p["k"], p["kT"])
+    assert abs(fl[-1] - (-2.0081)) < 5e-4 and abs(fl_l[-1] - (-1.9125)) < 5e-4
+
+
+def test_literal_estimators_match_their_expectations():
+    """The sampled literal estimators sit on the closed form for Gaussian windows."""
+    kappa, k, kT = 4.0, 20.0, 0.8
+    lam = np.array([-0.3, -0.15, 0.0, 0.12, 0.3])
+    Fc, mu, var = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    rng = np.random.default_rng(13)
+    smp = [rng.normal(m, np.sqrt(v), 50000) for m, v in zip(mu, var)]
+    p, xi, kept = _synthetic(smp, lam, k, kT, blocks=8, xi_bin=0.01)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    fl_l, g_l = quadrature.estimator_expectations_literal(lam, mu, var, k, kT)
+    assert np.allclose(r["dF_fluct_literal"], fl_l, atol=0.02)
+    assert np.allclose(r["dF_gauss_literal"], g_l, atol=0.02)
+
+
+def test_literal_work_binning_hand_case():
+    """One occupied x bin per window makes every work value deterministic.
+    Bin upper edges x = (b+1) dx, work in units of dW: f1 = dW_1(x)/dW = 2.7
+    then f2 = -3.4.  As printed: w2 = trunc(2.7) = 2, w3 = trunc(2 - 3.4) = -1,
+    then Omega_3(0) = (Omega_3(-1) + Omega_3(1))/2 = 1/2 (Omega_2(0) stays 0).
+    Floor instead would give 2 and then 2 + floor(-3.4) = -2."""
+    dWb, k = 0.1, 2.0
+    # x bin 3 of width 0.5 from 0: upper edge x = 2.0; choose lambdas so that
+    # k/2[(x - l2)^2 - (x - l1)^2] = 0.27 and then -0.34
+    x = 2.0
+    l1 = 0.0
+    # k/2 (l2^2 - l1^2) - k x (l2 - l1) = 0.27  ->  l2^2 - 4 l2 - 0.27 = 0
+    l2 = 2.0 - np.sqrt(4.0 + 0.27)
+    # k/2 (l3^2 - l2^2) - k x (l3 - l2) = -0.34 -> l3^2 - 4 l3 - (l2^2 - 4 l2 - 0.34) = 0
+    c = l2 ** 2 - 4 * l2 - 0.34
+    l3 = 2.0 - np.sqrt(4.0 + c)
+    p = {"lambda": [l1, l2, l3], "k": k, "kT": 1.0, "xi_min": 0.0, "xi_bin": 0.5, "xi_nbins": 6,
+         "w_bin": dWb, "w_half_bins": 10}
+    hist = np.zeros((3, 6), dtype=np.int64); hist[:, 3] = 7
+    out = appc.work_distributions_literal(p, hist, hist.sum(axis=1))
+    om = out["work_hist_literal"]; M = 10
+    assert om[1, M + 2] == 1.0 and om[1].sum() == 1.0
+    assert om[2, M - 1] == 1.0 and om[2, M] == 0.5 and om[2].sum() == 1.5
+    expect = -np.log((np.exp(0.1) + 0.5) / 1.5)
+    assert abs(out["dF_je_hist_literal"][2] - expect) < 1e-12
+    # with the bin centre (x = 1.75) as representative: f = 2.37, -2.98, so w3 = trunc(2 - 2.98) = 0
+    fc = [0.5 * k * ((1.75 - b) ** 2 - (1.75 - a) ** 2) / dWb for a, b in ((l1, l2), (l2, l3))]
+    assert int(np.trunc(np.trunc(fc[0]) + fc[1])) == 0
