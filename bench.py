@@ -29,8 +29,8 @@ FP64_PEAK = 78.6e12
 # 1024: FETCH_SIZE reads 524308 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  A record
 # holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain10": {"sources_sha1": "b6e2f2d4695a0dfecca36472dba5f9f9f5238311", "kernel": "sim_chain<float,5,2>",
-                "fetch_kib": 173.0, "fetch_scale": 2.0, "write_kib": 10146.125, "write_scale": 1.0},
+    "chain10": {"sources_sha1": "46bbfd2293500c5288d24c90c1b7bc42f5dd1f76", "kernel": "sim_chain<float,5,2>",
+                "fetch_kib": 179.0, "fetch_scale": 2.0, "write_kib": 10146.125, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
                   "ppp_launch.hpp")
@@ -204,6 +204,47 @@ def batch_bench(args, desc):
     print(json.dumps(out), flush=True)
 
 
+def sweep_study(args):
+    """Relaxation time and stiffness sweep (the analogues of the paper's tau and k
+    studies, Sec. IV C-D) on the 10-bead chain, every problem in one batched graph:
+    tau = 500 .. 40000 steps at k = 20, and k = 2 .. 200 at tau = 20000 steps, 21
+    windows in [1.5, 8.5], 4096 replicas per window."""
+    import numpy as np
+    import torch
+    import paper_1105_4840_amd as ppp
+    import ppp_inputs
+    taus = [500, 1000, 2000, 5000, 10000, 20000, 40000]
+    ks = [2.0, 5.0, 10.0, 20.0, 50.0, 100.0, 200.0]
+    probs, labels = [], []
+    for t in taus:
+        p = ppp_inputs.config_chain10(n_replicas=4096, n_steps=t, seed=11)
+        probs.append(p); labels.append({"tau_steps": t, "k": 20.0})
+    for k in ks:
+        p = ppp_inputs.config_chain10(n_replicas=4096, n_steps=20000, seed=12)
+        p["k"] = k
+        probs.append(p); labels.append({"tau_steps": 20000, "k": k})
+    h = ppp.ppp_batch_create(probs)
+    ws = ppp.workspace(h)
+    t0 = time.perf_counter()
+    ppp.ppp_run(h, ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rows = []
+    for i, (p, lab) in enumerate(zip(probs, labels)):
+        r = ppp.ppp_batch_get_result(h, p, i)
+        rows.append(dict(lab, dF_je=float(r["dF_je"][-1]), dF_je_se=float(r["dF_je_se"][-1]),
+                         dF_fluct=float(r["dF_fluct"][-1]), dF_gauss=float(r["dF_gauss"][-1]),
+                         dF_com=float(r["dF_com"][-1]), unc=float(r["dF_unc"][-1]),
+                         gamma2_mean=float(np.mean(r["gamma2"])),
+                         dl_over_sigma_max=float(np.max(r["dlambda_over_sigma"])),
+                         ovl_min=float(np.min(r["overlap_ovl"])), kish_min=float(np.min(r["kish_frac"])),
+                         criterion_ok=int(np.sum(r["criterion_ok"])), frozen=int(r["n_blown_up"].sum())))
+    ppp.ppp_destroy(h)
+    rs = sum(len(p["lambda"]) * p["n_replicas"] * p["n_steps"] for p in probs)
+    print(json.dumps({"study": "tau and k sweep, 10-bead chain, 21 windows in [1.5, 8.5], 4096 replicas/window, "
+                               "one batched graph", "replica_steps": rs, "seconds": el, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +257,7 @@ def main():
     ap.add_argument("--placement-study", action="store_true",
                     help="dF error at equal budget, uniform vs learned windows (32-bead chain)")
     ap.add_argument("--ref-steps", type=int, default=40000)
+    ap.add_argument("--sweep", action="store_true", help="tau and k sweep of the 10-bead chain in one batched graph")
     ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
     ap.add_argument("--sequential", action="store_true",
                     help="run the workload with the sequential pulling protocol (each replica runs the "
@@ -241,6 +283,10 @@ def main():
     if args.placement_study:
         torch.cuda.set_device(0)
         placement_study(args)
+        return
+    if args.sweep:
+        torch.cuda.set_device(0)
+        sweep_study(args)
         return
     fn, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)

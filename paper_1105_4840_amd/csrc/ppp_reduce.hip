@@ -253,128 +253,218 @@ hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, h
 }
 
 // ---------------------------------------------------------------------------
-// App. C.  For the step i -> i+1, every non-empty x bin b of rho_i shifts the
-// work by s_b = floor(dW_i(x_b) / dW) bins (x_b the bin centre) and carries
-// probability rho_i(b); runs of equal shift are merged (s_b is monotone in b).
-__global__ void k_appc_pairs(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+// App. C.  For the step i -> i+1, every non-empty x bin b of rho_i moves the work
+// by a whole number of bins and carries probability rho_i(b); consecutive
+// non-empty bins with the same move are merged into one (shift, probability)
+// pair (the move is monotone in b).  Chain 0: x at the bin centre, move
+// floor(dW_i(x) / dW).  Chain 1, the listing as printed: x at the bin's upper
+// edge and truncation toward zero of W = w dW + dW_i(x), i.e. the move is
+// floor(f) for w + f >= 0 and ceil(f) below, f = dW_i(x) / dW; its pairs keep
+// both and merge only where both agree.
+//
+// One 256-thread block per (window step, problem, chain).  The bins are taken 256
+// at a time: the non-empty ones are compacted in order, run heads are marked, and
+// each head sums its run left to right, the first run of a chunk continuing the
+// last one of the previous chunk where the shifts agree, so every probability is
+// the same left-to-right sum as in a sequential pass.
+__device__ __forceinline__ int block_excl_scan(int v, int *sh, int &total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[255];
+    const int r = sh[t] - v;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int clamp_shift(double f) {
+    return f > 2.0e9 ? 2000000000 : (f < -2.0e9 ? -2000000000 : (int)f);
+}
+
+__global__ __launch_bounds__(256) void k_appc_pairs(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
 #pragma clang fp contract(off)
     const DevProblem &P = probs[blockIdx.y];
-    const int i = blockIdx.x;
-    if (P.w_half_bins <= 0 || i + 1 >= P.n_windows || threadIdx.x > 1) return;
-    if (threadIdx.x == 1) {
-        // chain 1, the listing as printed: x at the bin's upper edge; the pair's work
-        // W = w dW + dW_i(x) goes to bin trunc(W / dW), i.e. w + floor(f) where
-        // w + f >= 0 and w + ceil(f) below, f = dW_i(x) / dW
-        const int K = P.xi_nbins;
-        const double *lam = dptr(ws, P.off_lambda);
-        const double *tot = dptr(ws, P.off_tot);
-        const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)i * K;
-        const int64_t sK = (int64_t)P.n_windows * K;
-        int *fl = reinterpret_cast<int *>(ws + P.off_pairs_shift) + sK + (int64_t)i * K;
-        int *ce = reinterpret_cast<int *>(ws + P.off_pairs_ceil) + (int64_t)i * K;
-        double *prob = dptr(ws, P.off_pairs_prob) + sK + (int64_t)i * K;
-        const double n = tot[(int64_t)i * A_NFIELDS + A_N];
-        const double li = lam[i], lj = lam[i + 1];
-        int np = 0;
-        for (int b = 0; b < K; ++b) {
-            const unsigned long long c = hist[b];
-            if (c == 0ull) continue;
-            const double xb = P.xi_min + ((double)b + 1.0) * P.xi_bin;
-            const double f = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li)) / P.w_bin;
-            const double ff = floor(f), fc = ceil(f);
-            const int sf = ff > 2.0e9 ? 2000000000 : (ff < -2.0e9 ? -2000000000 : (int)ff);
-            const int sc = fc > 2.0e9 ? 2000000000 : (fc < -2.0e9 ? -2000000000 : (int)fc);
-            const double pb = (double)c / n;
-            if (np > 0 && fl[np - 1] == sf && ce[np - 1] == sc) prob[np - 1] += pb;
-            else { fl[np] = sf; ce[np] = sc; prob[np] = pb; ++np; }
-        }
-        reinterpret_cast<int *>(ws + P.off_npairs)[P.n_windows + i] = np;
-        return;
-    }
+    const int i = blockIdx.x, chain = blockIdx.z, t = threadIdx.x;
+    if (P.w_half_bins <= 0 || i + 1 >= P.n_windows) return;
     const int K = P.xi_nbins;
+    const int64_t sK = (int64_t)P.n_windows * K;
     const double *lam = dptr(ws, P.off_lambda);
     const double *tot = dptr(ws, P.off_tot);
     const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)i * K;
-    int *shift = reinterpret_cast<int *>(ws + P.off_pairs_shift) + (int64_t)i * K;
-    double *prob = dptr(ws, P.off_pairs_prob) + (int64_t)i * K;
+    int *key0 = reinterpret_cast<int *>(ws + P.off_pairs_shift) + chain * sK + (int64_t)i * K;
+    int *key1 = reinterpret_cast<int *>(ws + P.off_pairs_ceil) + (int64_t)i * K;   // chain 1 only
+    double *prob = dptr(ws, P.off_pairs_prob) + chain * sK + (int64_t)i * K;
     const double n = tot[(int64_t)i * A_NFIELDS + A_N];
     const double li = lam[i], lj = lam[i + 1];
-    int np = 0;
-    for (int b = 0; b < K; ++b) {
-        const unsigned long long c = hist[b];
-        if (c == 0ull) continue;
-        const double xb = P.xi_min + ((double)b + 0.5) * P.xi_bin;
-        const double dW = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li));
-        const double fs = floor(dW / P.w_bin);
-        const int sb = fs > 2.0e9 ? 2000000000 : (fs < -2.0e9 ? -2000000000 : (int)fs);
-        const double pb = (double)c / n;
-        if (np > 0 && shift[np - 1] == sb) prob[np - 1] += pb;
-        else { shift[np] = sb; prob[np] = pb; ++np; }
+    __shared__ int s_scan[256];
+    __shared__ int s_k0[256], s_k1[256], s_head[256];
+    __shared__ double s_pb[256];
+    int np = 0, last0 = 0, last1 = 0;
+    for (int c0 = 0; c0 < K; c0 += 256) {
+        const int b = c0 + t;
+        const unsigned long long c = b < K ? hist[b] : 0ull;
+        int k0 = 0, k1 = 0;
+        double pb = 0.0;
+        if (c != 0ull) {
+            pb = (double)c / n;
+            if (chain == 0) {
+                const double xb = P.xi_min + ((double)b + 0.5) * P.xi_bin;
+                const double dW = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li));
+                k0 = k1 = clamp_shift(floor(dW / P.w_bin));
+            } else {
+                const double xb = P.xi_min + ((double)b + 1.0) * P.xi_bin;
+                const double f = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li)) / P.w_bin;
+                k0 = clamp_shift(floor(f));
+                k1 = clamp_shift(ceil(f));
+            }
+        }
+        int nnz;
+        const int pos = block_excl_scan(c != 0ull ? 1 : 0, s_scan, nnz);
+        if (c != 0ull) { s_k0[pos] = k0; s_k1[pos] = k1; s_pb[pos] = pb; }
+        __syncthreads();
+        int head = 0;
+        if (t < nnz) {
+            const int p0 = t ? s_k0[t - 1] : last0, p1 = t ? s_k1[t - 1] : last1;
+            head = (t == 0 && np == 0) || s_k0[t] != p0 || s_k1[t] != p1;
+            s_head[t] = head;
+        }
+        int nheads;
+        const int rid = block_excl_scan(head, s_scan, nheads);
+        if (head) {
+            double p = s_pb[t];
+            for (int m = t + 1; m < nnz && !s_head[m]; ++m) p += s_pb[m];
+            key0[np + rid] = s_k0[t];
+            if (chain) key1[np + rid] = s_k1[t];
+            prob[np + rid] = p;
+        } else if (t == 0 && nnz > 0) {
+            // the chunk opens inside the previous chunk's last run
+            double p = prob[np - 1];
+            for (int m = 0; m < nnz && !s_head[m]; ++m) p += s_pb[m];
+            prob[np - 1] = p;
+        }
+        if (nnz > 0) { last0 = s_k0[nnz - 1]; last1 = s_k1[nnz - 1]; }
+        np += nheads;
+        __syncthreads();
     }
-    reinterpret_cast<int *>(ws + P.off_npairs)[i] = np;
+    if (t == 0) reinterpret_cast<int *>(ws + P.off_npairs)[chain * P.n_windows + i] = np;
 }
 
 // Omega_j(w) = sum_t prob_t Omega_{j-1}(w - shift_t), the folding step of App. C.
 // Chain 1 (blockIdx.z) folds as printed: target w > 0 takes source w - floor(f),
-// w < 0 takes w - ceil(f), and w = 0 both (the spike of truncation), and its
-// Omega_j(0) is then replaced by the mean of Omega_j(-1) and Omega_j(1).
+// w < 0 takes w - ceil(f); at w = 0 the printed step keeps the mean of the
+// results at w = -1 and w = +1 instead, which are exactly what the targets -1 and
+// +1 compute, so the bin is left unsmoothed here and every reader of Omega_j
+// (j >= 1) of chain 1 takes the mean of its neighbours there (omega_at).
+//
+// A block owns 256 consecutive target bins.  Pairs are taken 256 at a time; for
+// each, the sources that the block's targets read lie in 259 consecutive bins
+// (one spare on either side), which are staged in LDS together with those of
+// the other pairs of the chunk, so the inner loop is one LDS read and one FMA per
+// pair.  Pairs whose sources cannot all share one staging window of kAppcStage
+// bins are taken in further windows; pairs whose sources lie wholly outside the
+// histogram get weight 0.  With one window the sums run in pair order.
+constexpr int kAppcStage = 4096;
+constexpr int kAppcSpan = 259;                  // sources of one pair for one block
+
+__device__ __forceinline__ double omega_at(const double *om, int64_t b, int M, bool smooth) {
+    return (smooth && b == M) ? 0.5 * (om[M - 1] + om[M + 1]) : om[b];
+}
+
+__device__ __forceinline__ int64_t block_min_max(int64_t v, bool is_min, int64_t *sh) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off);
+        v = is_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t r = sh[0];
+    for (int q = 1; q < 4; ++q) r = is_min ? (sh[q] < r ? sh[q] : r) : (sh[q] > r ? sh[q] : r);
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_appc_step(const DevProblem *__restrict__ probs, char *__restrict__ ws, int j) {
     const DevProblem &P = probs[blockIdx.y];
     if (P.w_half_bins <= 0 || j >= P.n_windows) return;
     const int chain = blockIdx.z;
     const int M = P.w_half_bins;
     const int64_t nb = 2 * (int64_t)M + 1;
+    const int64_t w0 = (int64_t)blockIdx.x * 256;
+    if (w0 >= nb) return;
     const int64_t sK = (int64_t)P.n_windows * P.xi_nbins;
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = w0 + threadIdx.x;
     const int np = reinterpret_cast<const int *>(ws + P.off_npairs)[chain * P.n_windows + j - 1];
     const int *shift = reinterpret_cast<const int *>(ws + P.off_pairs_shift) + chain * sK + (int64_t)(j - 1) * P.xi_nbins;
     const int *ceil_s = reinterpret_cast<const int *>(ws + P.off_pairs_ceil) + (int64_t)(j - 1) * P.xi_nbins;
     const double *prob = dptr(ws, P.off_pairs_prob) + chain * sK + (int64_t)(j - 1) * P.xi_nbins;
     const double *prev = dptr(ws, P.off_omega) + chain * (int64_t)P.n_windows * nb + (int64_t)(j - 1) * nb;
     double *cur = dptr(ws, P.off_omega) + chain * (int64_t)P.n_windows * nb + (int64_t)j * nb;
-    __shared__ int s_shift[256];
-    __shared__ int s_ceil[256];
+    const bool smooth_prev = chain == 1 && j >= 2;
+    __shared__ int s_sf[256], s_sc[256], s_win[256];
     __shared__ double s_prob[256];
-    const int64_t wv = w - M;                 // work bin of this thread
-    double acc = 0.0, acc_m = 0.0, acc_p = 0.0;   // chain 1 at W = 0 also needs bins -1 and +1
+    __shared__ int64_t s_red[4];
+    __shared__ double s_src[kAppcStage];
+    // chain 1 below W = 0 reads through ceil(f), everything else through floor(f)
+    const int *sel = (chain == 1 && w < M) ? s_sc : s_sf;
+    constexpr int64_t kNone = INT64_MAX;
+    constexpr int64_t step = kAppcStage - kAppcSpan;
+    double acc = 0.0;
     for (int t0 = 0; t0 < np; t0 += 256) {
         const int cnt = np - t0 < 256 ? np - t0 : 256;
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            s_shift[threadIdx.x] = shift[t0 + threadIdx.x];
-            s_ceil[threadIdx.x] = chain ? ceil_s[t0 + threadIdx.x] : 0;
-            s_prob[threadIdx.x] = prob[t0 + threadIdx.x];
+        const int t = threadIdx.x;
+        int sf = 0, sc = 0;
+        double pt = 0.0;
+        int64_t first = kNone;
+        if (t < cnt) {
+            sf = shift[t0 + t];
+            sc = chain ? ceil_s[t0 + t] : sf;
+            pt = prob[t0 + t];
+            first = w0 - 1 - (int64_t)(sc > sf ? sc : sf);
+            if (first + kAppcSpan <= 0 || first >= nb) first = kNone;    // reads nothing in range
         }
-        __syncthreads();
-        if (w < nb) {
-            if (chain == 0) {
-                for (int t = 0; t < cnt; ++t) {
-                    const int64_t src = w - s_shift[t];
-                    if (src >= 0 && src < nb) acc += s_prob[t] * prev[src];
-                }
-            } else {
-                for (int t = 0; t < cnt; ++t) {
-                    const int sf = s_shift[t], sc = s_ceil[t];
-                    const double pt = s_prob[t];
-                    if (wv > 0) {
-                        const int64_t src = w - sf;
-                        if (src >= 0 && src < nb) acc += pt * prev[src];
-                    } else if (wv < 0) {
-                        const int64_t src = w - sc;
-                        if (src >= 0 && src < nb) acc += pt * prev[src];
-                    } else {
-                        const int64_t s1 = M - (int64_t)sf, s2 = M - (int64_t)sc;
-                        if (s1 >= 0 && s1 < nb) acc += pt * prev[s1];
-                        if (sc != sf && s2 >= 0 && s2 < nb) acc += pt * prev[s2];
-                        const int64_t sm = M - 1 - (int64_t)sc, sp = M + 1 - (int64_t)sf;   // bins -1 and +1
-                        if (sm >= 0 && sm < nb) acc_m += pt * prev[sm];
-                        if (sp >= 0 && sp < nb) acc_p += pt * prev[sp];
-                    }
+        const int64_t base = block_min_max(first, true, s_red);
+        if (base == kNone) continue;                                      // uniform
+        const int64_t top = block_min_max(first == kNone ? INT64_MIN : first, false, s_red);
+        if (t < cnt) {
+            if (first == kNone) {          // weight 0, reading a staged bin of the first window
+                sf = sc = (int)(w0 - 1 - base);
+                pt = 0.0;
+                first = base;
+            }
+            s_sf[t] = sf;
+            s_sc[t] = sc;
+            s_prob[t] = pt;
+            s_win[t] = (int)((first - base) / step);
+        }
+        const int n_win = (int)((top - base) / step) + 1;
+        for (int win = 0; win < n_win; ++win) {
+            const int64_t start = base + (int64_t)win * step;
+            const int64_t len = top - start + kAppcSpan < kAppcStage ? top - start + kAppcSpan : kAppcStage;
+            for (int q = threadIdx.x; q < len; q += 256) {
+                const int64_t src = start + q;
+                s_src[q] = (src >= 0 && src < nb) ? omega_at(prev, src, M, smooth_prev) : 0.0;
+            }
+            __syncthreads();
+            if (w < nb) {
+                const int off = (int)(w - start);   // s_src[off - s] = Omega_{j-1}(w - s)
+                if (n_win == 1) {
+#pragma unroll 8
+                    for (int u = 0; u < cnt; ++u) acc += s_prob[u] * s_src[off - sel[u]];
+                } else {
+                    for (int u = 0; u < cnt; ++u)
+                        if (s_win[u] == win) acc += s_prob[u] * s_src[off - sel[u]];
                 }
             }
+            __syncthreads();
         }
     }
-    if (w < nb) cur[w] = (chain == 1 && wv == 0) ? 0.5 * (acc_m + acc_p) : acc;
+    if (w < nb) cur[w] = acc;
 }
 
 // Statistics of Omega_j: normalised exponential average (App. B.5), spread and
@@ -393,8 +483,9 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
     const double beta = P.beta, dWb = P.w_bin;
     const double shift_mid = 0.5 * (double)j * dWb;
     double tot = 0, q = 0, mw = 0, emax = -INFINITY;
+    const bool smooth = chain == 1 && j >= 1;   // chain 1 keeps W = 0 unsmoothed in memory
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        const double o = om[b];
+        const double o = omega_at(om, b, M, smooth);
         if (o != 0.0) {
             const double W = (double)(b - M) * dWb;
             tot += o; q += 1.0; mw += o * W;
@@ -416,7 +507,7 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
     const double mean = mw / tot;
     double sl = 0, sm = 0, vv = 0;
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        const double o = om[b];
+        const double o = omega_at(om, b, M, smooth);
         if (o != 0.0) {
             const double W = (double)(b - M) * dWb;
             sl += o * exp(-beta * W - emax);
@@ -446,7 +537,7 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
 hipError_t launch_appc(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_m,
                        hipStream_t stream) {
     if (max_m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_appc_pairs, dim3(max_windows, n_probs), dim3(64), 0, stream, d_probs, ws);
+    hipLaunchKernelGGL(k_appc_pairs, dim3(max_windows, n_probs, 2), dim3(256), 0, stream, d_probs, ws);
     const int64_t nb = 2 * (int64_t)max_m + 1;
     const int grid = (int)((nb + 255) / 256);
     for (int j = 1; j < max_windows; ++j)
