@@ -105,7 +105,7 @@ typedef struct {
     int32_t w_half_bins;         /* M >= 0: 2M+1 work bins; 0 disables App. C */
     int32_t n_jack_blocks;       /* jackknife blocks B in [0, 4096] (0: 32); above n_replicas: n_replicas */
     double xi_bound;             /* |xi| above this freezes a replica (<= 0: 1e4) */
-    uint32_t flags;              /* 0 or PPP_FLAG_SEQUENTIAL */
+    uint32_t flags;              /* 0, or PPP_FLAG_SEQUENTIAL or PPP_FLAG_FREE_ENSEMBLE */
 } ppp_problem;
 
 /* Sequential pulling protocol (Sec. III(i), Fig. 1b) instead of the parallel
@@ -121,6 +121,36 @@ typedef struct {
  * protocols.  Not available for batched or adaptive runs, nor for
  * ppp_trajectory. */
 #define PPP_FLAG_SEQUENTIAL 1u
+
+/* Turn-on free energy (Sec. II, Eqs. 4-7 and 10; App. A; the state function
+ * G of Eq. 15).  Besides the s restrained windows the run simulates the
+ * unrestrained system H_o (k = 0): n_replicas more replicas from the same
+ * start state with the same step schedule, numbered after those of window s
+ * (replica r has noise counters of replica number s R + r).  Their samples
+ * x_0 and those of windows 1 and s give ppp_result.turn_on:
+ *   DF(lambda_1, k) = F(lambda_1, k) - F_0 by Eq. 5 (an average over window
+ *   1 of exp(+beta k/2 (x_1 - lambda_1)^2)) and by Eq. 6 (an average over x_0
+ *   of exp(-beta k/2 (x_0 - lambda_1)^2)), each with its jackknife error, and
+ *   the two bounds of Eq. 7; the same at lambda_s from window s and x_0;
+ *   ln <exp(-beta W_total)> of Eq. 10 with the average factorised over the
+ *   independent ensembles x_0, x_1 .. x_s (0 in expectation);
+ *   the free ensemble's sample count, frozen replicas, mean and spread of xi;
+ * and ppp_result.G[j] = dF_je[j] - DF(lambda_1, k) with DF by Eq. 5, the state
+ * function of Eq. 15.  The per-window profiles do not change.  Not available
+ * with PPP_FLAG_SEQUENTIAL or for adaptive runs (PPP_E_UNSUPPORTED);
+ * ppp_trajectory serves the restrained windows only. */
+#define PPP_FLAG_FREE_ENSEMBLE 2u
+
+/* Entries of ppp_result.turn_on ("first": lambda_1, "last": lambda_s). */
+enum {
+    PPP_ON_EQ5_FIRST = 0, PPP_ON_EQ5_FIRST_SE, PPP_ON_EQ6_FIRST, PPP_ON_EQ6_FIRST_SE,
+    PPP_ON_LOWER_FIRST, PPP_ON_UPPER_FIRST,          /* Eq. 7: <k/2 (x_1 - l)^2>_l and <k/2 (x_0 - l)^2>_0 */
+    PPP_ON_EQ5_LAST, PPP_ON_EQ5_LAST_SE, PPP_ON_EQ6_LAST, PPP_ON_EQ6_LAST_SE,
+    PPP_ON_LOWER_LAST, PPP_ON_UPPER_LAST,
+    PPP_ON_EQ10_LOG, PPP_ON_EQ10_LOG_SE,
+    PPP_ON_FREE_N, PPP_ON_FREE_BLOWN, PPP_ON_FREE_MEAN, PPP_ON_FREE_STD, PPP_ON_FREE_UNDER, PPP_ON_FREE_OVER,
+    PPP_ON_NFIELDS
+};
 
 /* Caller-owned host output buffers; any pointer may be NULL (not wanted).
  * s = n_windows, K = xi_nbins, M = w_half_bins.  Profiles are relative to
@@ -162,6 +192,10 @@ typedef struct {
     uint64_t *xi_hist;                 /* [s*K] */
     uint64_t *xi_under_over;           /* [s*2] */
     double *work_hist;                 /* [s*(2M+1)], Omega_j, bin w at index w + M */
+    /* with PPP_FLAG_FREE_ENSEMBLE (else filled with NaN, and zero counts) */
+    double *turn_on;                   /* [PPP_ON_NFIELDS] */
+    double *G, *G_se;                  /* [s] Eq. 15 */
+    uint64_t *xi_hist_free;            /* [K] histogram of x_0 */
 } ppp_result;
 
 typedef struct {
@@ -183,7 +217,8 @@ typedef struct ppp_handle ppp_handle;
  * n_equil < 0 or >= n_steps, K < 1, xi_bin <= 0, w_bin <= 0 with M > 0,
  * chain with n_beads < 2 or > PPP_MAX_BEADS, non-positive mass or bond
  * length, unknown flags, or a sequential run of more than 2^32 - 1 steps per
- * replica.  *out is NULL on failure. */
+ * replica; PPP_E_UNSUPPORTED for PPP_FLAG_SEQUENTIAL with
+ * PPP_FLAG_FREE_ENSEMBLE.  *out is NULL on failure. */
 ppp_status ppp_create(const ppp_problem *p, ppp_handle **out);
 
 /* Batched form (uneven chains, windows, replicas, steps): all problems run in

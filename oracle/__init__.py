@@ -47,6 +47,7 @@ class OracleProblem(ctypes.Structure):
         ("xi_bound", ctypes.c_double),
         ("n_pull", ctypes.c_int64),
         ("sequential", ctypes.c_int32),
+        ("free_ensemble", ctypes.c_int32),
     ]
 
 
@@ -110,6 +111,7 @@ class _Problem:
             xi_bound=float(prob.get("xi_bound", 1.0e4)),
             n_pull=int(prob.get("n_pull", 0)),
             sequential=1 if prob.get("sequential", False) else 0,
+            free_ensemble=1 if prob.get("free_ensemble", False) else 0,
         )
 
     def ref(self):
@@ -163,7 +165,7 @@ def run(prob: dict, n_threads: int = 0):
     """Runs every replica of every window; returns (xi [W*R, S], n_kept [W*R], threads)."""
     P = _Problem(prob)
     S = int(lib().oracle_samples_per_replica(P.ref()))
-    total = len(P.lam) * int(prob["n_replicas"])
+    total = (len(P.lam) + (1 if prob.get("free_ensemble", False) else 0)) * int(prob["n_replicas"])
     xi = np.full((total, max(S, 1)), np.nan)
     kept = np.zeros(total, dtype=np.int64)
     used = lib().oracle_run(P.ref(), _dp(xi), kept.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

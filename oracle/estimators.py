@@ -15,7 +15,11 @@ the definitions in the paper (arXiv:1105.4840):
   (dF^JE - dF_fluct)/2 (Sec. IV B and IV D);
 * gamma_i^2 = k sigma_i^2 / kT (Sec. II, below Eq. 12);
 * jackknife standard errors over replica blocks, the JE variance formula of
-  Sec. IV A / App. C, Kish effective sample size and adjacent-window overlap.
+  Sec. IV A / App. C, Kish effective sample size and adjacent-window overlap;
+* with the unrestrained ensemble x_0 sampled as well (Sec. II): the turn-on
+  free energy dF(lambda, k) = F(lambda, k) - F_0 by Eq. 5 (restrained window)
+  and by Eq. 6 (x_0), the bounds of Eq. 7, the average of Eq. 10 over the
+  independent ensembles x_0, x_1 .. x_s, and G of Eq. 15.
 """
 import numpy as np
 
@@ -108,6 +112,71 @@ def profiles(stats, lam, k, kT):
             "dF_fluct_literal": fl_lit, "dF_gauss_literal": g_lit}
 
 
+def turn_on_values(x1, xs, x0, lam, k, kT, je_s):
+    """Turn-on estimates from the samples of window 1 (x1), window s (xs) and the
+    unrestrained ensemble (x0); je_s = dF^JE(lambda_s) of the same samples."""
+    beta = 1.0 / kT
+    l1, ls = lam[0], lam[-1]
+    out = {}
+    # Eq. 5: exp(beta dF) = < exp(+beta k/2 (x - lambda)^2) > in the restrained ensemble
+    out["eq5_first"] = kT * (logsumexp(0.5 * beta * k * (x1 - l1) ** 2) - np.log(x1.size))
+    out["eq5_last"] = kT * (logsumexp(0.5 * beta * k * (xs - ls) ** 2) - np.log(xs.size))
+    # Eq. 6: exp(-beta dF) = < exp(-beta k/2 (x_0 - lambda)^2) > in the unrestrained ensemble
+    out["eq6_first"] = -kT * (logsumexp(-0.5 * beta * k * (x0 - l1) ** 2) - np.log(x0.size))
+    out["eq6_last"] = -kT * (logsumexp(-0.5 * beta * k * (x0 - ls) ** 2) - np.log(x0.size))
+    # Eq. 10: W_total = k/2 (x_0 - lambda_1)^2 + W_mech - k/2 (x_s - lambda_s)^2 with every
+    # x_i from its own ensemble, so the average factorises
+    out["eq10_log"] = -beta * (out["eq6_first"] + je_s - out["eq5_last"])
+    return out
+
+
+def turn_on(prob, xi, kept, je):
+    """Turn-on outputs (Eqs. 5-7, 10) with jackknife errors, and G of Eq. 15 with its
+    error; je is the dF^JE profile of the same samples."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    k = float(prob["k"]); kT = float(prob["kT"])
+    s = len(lam)
+    R = int(prob["n_replicas"])
+    B = max(1, min(int(prob.get("n_blocks", 32)), R))
+    x1, xs, x0 = (pooled(xi, kept, w, R) for w in (0, s - 1, s))
+    res = turn_on_values(x1, xs, x0, lam, k, kT, je[-1])
+    # Eq. 15: G(lambda_j, lambda_1) = dF^JE(lambda_j) - dF(lambda_1, k), dF by Eq. 5
+    G = je - res["eq5_first"]
+    # Eq. 7: <k/2 (x_1 - lambda)^2>_lambda <= dF(lambda, k) <= <k/2 (x_0 - lambda)^2>_0
+    res["lower_first"] = 0.5 * k * np.mean((x1 - lam[0]) ** 2)
+    res["upper_first"] = 0.5 * k * np.mean((x0 - lam[0]) ** 2)
+    res["lower_last"] = 0.5 * k * np.mean((xs - lam[-1]) ** 2)
+    res["upper_last"] = 0.5 * k * np.mean((x0 - lam[-1]) ** 2)
+    res["free_n"] = x0.size
+    res["free_mean"] = np.mean(x0)
+    res["free_std"] = np.std(x0, ddof=1)
+    keys = ("eq5_first", "eq6_first", "eq5_last", "eq6_last", "eq10_log")
+    if B > 1:
+        blocks = block_of(np.arange(R), R, B)
+        loo = {key: [] for key in keys + ("G",)}
+        for b in range(B):
+            keep_reps = np.nonzero(blocks != b)[0]
+            st_b = [window_stats(pooled(xi, kept, w, R, keep_reps), w, lam, k, kT) for w in range(s)]
+            je_b = profiles(st_b, lam, k, kT)["dF_je"]
+            xb = [pooled(xi, kept, w, R, keep_reps) for w in (0, s - 1, s)]
+            v = turn_on_values(*xb, lam, k, kT, je_b[-1])
+            v["G"] = je_b - v["eq5_first"]
+            for key in loo:
+                loo[key].append(v[key])
+        se = {}
+        for key in loo:
+            th = np.array(loo[key])
+            se[key] = np.sqrt((B - 1) / B * np.sum((th - th.mean(axis=0)) ** 2, axis=0))
+        for key in keys:
+            res[key + "_se"] = float(se[key])
+        G_se = se["G"]
+    else:
+        for key in keys:
+            res[key + "_se"] = np.nan
+        G_se = np.full(s, np.nan)
+    return res, G, G_se
+
+
 def histograms(xi, kept, prob):
     """Counts of xi in K bins of width dxi from xi_min; bin b = floor((xi - xi_min)/dxi)."""
     lam = np.asarray(prob["lambda"], dtype=np.float64)
@@ -191,4 +260,14 @@ def estimate(prob, xi, kept, with_appc=True):
     if with_appc and int(prob.get("w_half_bins", 0)) > 0:
         res.update(appc.work_distributions(prob, hist, n))
         res.update(appc.work_distributions_literal(prob, hist, n))
+    if prob.get("free_ensemble", False):
+        on, res["G"], res["G_se"] = turn_on(prob, xi, kept, res["dF_je"])
+        res["turn_on"] = on
+        x0 = pooled(xi, kept, s, R)
+        b0 = np.floor((x0 - float(prob["xi_min"])) / float(prob["xi_bin"])).astype(np.int64)
+        K = int(prob["xi_nbins"])
+        res["xi_hist_free"] = np.bincount(b0[(b0 >= 0) & (b0 < K)], minlength=K)
+        on["free_under"] = int(np.count_nonzero(b0 < 0))
+        on["free_over"] = int(np.count_nonzero(b0 >= K))
+        on["free_blown"] = int(np.count_nonzero(kept[s * R:(s + 1) * R] < (xi.shape[1] if xi.ndim == 2 else 0)))
     return res

@@ -54,6 +54,8 @@ typedef struct {
     double xi_bound;        /* |xi| above this (or non-finite state) freezes a replica */
     int64_t n_pull;         /* steps over which the centre moves from xi(x_o) to lambda_i (0: switched on at once) */
     int32_t sequential;     /* 1: sequential pulling protocol (Sec. III(i)) instead of the parallel one */
+    int32_t free_ensemble;  /* 1: also sample the unrestrained system H_o (Sec. II, Eq. 6) as an extra
+                               window numbered n_windows, restraint k = 0 */
 } oracle_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -260,7 +262,7 @@ int64_t oracle_samples_per_replica(const oracle_problem *p)
 static int64_t run_replica_1d(const oracle_problem *p, int window, int replica,
                               double *xi_out, double *traj, int64_t traj_steps)
 {
-    const double lam = p->lambda[window];
+    const double lam = window < p->n_windows ? p->lambda[window] : p->lambda[0];
     const uint32_t gid = (uint32_t)((int64_t)window * p->n_replicas + replica);
     double x = p->init_coords ? p->init_coords[0] : p->lambda[0];
     const double x_start = x;
@@ -290,7 +292,7 @@ static int64_t run_replica_chain(const oracle_problem *p, int window, int replic
                                  double *xi_out, double *traj, int64_t traj_steps)
 {
     const int N = p->n_beads;
-    const double lam = p->lambda[window];
+    const double lam = window < p->n_windows ? p->lambda[window] : p->lambda[0];
     const uint32_t gid = (uint32_t)((int64_t)window * p->n_replicas + replica);
     double *r = (double *)malloc(sizeof(double) * 3 * N);
     double *v = (double *)calloc(3 * N, sizeof(double));
@@ -435,13 +437,17 @@ static void run_sequential_chain(const oracle_problem *p, int replica, double *x
     free(r); free(v); free(f);
 }
 
-/* Runs every replica of every window.  xi_out is [n_windows*n_replicas][S]
- * with S = oracle_samples_per_replica(p); n_kept is [n_windows*n_replicas].
+/* Runs every replica of every window.  xi_out is [W*n_replicas][S] with
+ * W = n_windows (+1 with the free ensemble) and S = oracle_samples_per_replica(p);
+ * n_kept is [W*n_replicas].
  * Returns the number of host threads used. */
 int oracle_run(const oracle_problem *p, double *xi_out, int64_t *n_kept, int n_threads)
 {
     const int64_t S = oracle_samples_per_replica(p);
-    const int64_t total = (int64_t)p->n_windows * p->n_replicas;
+    /* the unrestrained ensemble is window n_windows: the same system with k = 0 */
+    const int64_t total = ((int64_t)p->n_windows + (p->free_ensemble ? 1 : 0)) * p->n_replicas;
+    oracle_problem free_sys = *p;
+    free_sys.k = 0.0;
     int used = 1;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -462,9 +468,10 @@ int oracle_run(const oracle_problem *p, double *xi_out, int64_t *n_kept, int n_t
 #pragma omp for schedule(dynamic, 1)
             for (int64_t g = 0; g < total; ++g) {
                 int window = (int)(g / p->n_replicas), replica = (int)(g % p->n_replicas);
+                const oracle_problem *q = window < p->n_windows ? p : &free_sys;
                 double *dst = xi_out + g * S;
-                n_kept[g] = (p->model == 0) ? run_replica_1d(p, window, replica, dst, NULL, 0)
-                                            : run_replica_chain(p, window, replica, dst, NULL, 0);
+                n_kept[g] = (p->model == 0) ? run_replica_1d(q, window, replica, dst, NULL, 0)
+                                            : run_replica_chain(q, window, replica, dst, NULL, 0);
             }
         }
     }

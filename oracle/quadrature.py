@@ -122,3 +122,26 @@ def estimator_expectations_literal(lam, mu, var, k, kT):
         fl[j] = k * span * np.sum(lam[:j] - mu[:j]) / (j + 1)
         g[j] = k * span ** 2 / (2.0 * (j + 1)) * np.sum(1.0 - k * np.asarray(var[:j]) / kT) / (j + 1) + fl[j]
     return fl, g
+
+
+def turn_on_1d(U, lam, k, kT, lo=-4.0, hi=4.0, n_panels=4000):
+    """Turn-on free energy dF(lambda, k) = F(lambda, k) - F_0 of one particle in U(x)
+    (Eqs. 5-6, with F_0 = -kT ln int exp(-beta U)), and the two sides of Eq. 7:
+    <k/2 (x - lambda)^2> over the restrained and over the unrestrained density."""
+    x, w = _panels(lo, hi, n_panels)
+    beta = 1.0 / kT
+    Ux = U(x)
+    lz0, m0, v0 = _moments(x, w, -beta * Ux)
+    lam = np.atleast_1d(np.asarray(lam, dtype=np.float64))
+    F, mu, var = restrained_1d(U, lam, k, kT, lo, hi, n_panels)
+    dF = F + kT * lz0
+    lower = 0.5 * k * (var + (mu - lam) ** 2)
+    upper = 0.5 * k * (v0 + (m0 - lam) ** 2)
+    return dF, lower, upper
+
+
+def harmonic_turn_on_closed_form(kappa, k, kT, lam):
+    """dF(lambda, k) for H_o = kappa/2 x^2: the ratio of two Gaussian integrals,
+    kT/2 ln((kappa + k)/kappa) + kappa k lambda^2 / (2 (kappa + k))."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return 0.5 * kT * np.log((kappa + k) / kappa) + kappa * k * lam ** 2 / (2.0 * (kappa + k))

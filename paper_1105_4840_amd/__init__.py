@@ -16,6 +16,12 @@ LIB_PATH = os.path.join(_HERE, "libppp.so")
 
 PPP_OK, PPP_E_INVALID_ARG, PPP_E_OUT_OF_MEMORY, PPP_E_DEVICE, PPP_E_NUMERICAL, PPP_E_STATE, PPP_E_UNSUPPORTED = range(7)
 PPP_FLAG_SEQUENTIAL = 1
+PPP_FLAG_FREE_ENSEMBLE = 2
+# entries of the turn-on array (include/ppp.h, PPP_ON_*)
+TURN_ON_FIELDS = ["eq5_first", "eq5_first_se", "eq6_first", "eq6_first_se", "lower_first", "upper_first",
+                  "eq5_last", "eq5_last_se", "eq6_last", "eq6_last_se", "lower_last", "upper_last",
+                  "eq10_log", "eq10_log_se", "free_n", "free_blown", "free_mean", "free_std", "free_under",
+                  "free_over"]
 PPP_MLP_HIDDEN = 64
 PPP_MLP_PARAMS = 64 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -69,7 +75,8 @@ class ppp_result(ctypes.Structure):
     _fields_ = ([(n, _dp) for n in _RESULT_S] + [(n, _i64p) for n in _RESULT_S_I64] +
                 [(n, _dp) for n in _RESULT_S2] + [(n, _i64p) for n in _RESULT_S_I64_2] +
                 [(n, _dp) for n in _RESULT_P] + [("criterion_ok", _i32p)] + [(n, _dp) for n in _RESULT_LIT] +
-                [("xi_hist", _u64p), ("xi_under_over", _u64p), ("work_hist", _dp)])
+                [("xi_hist", _u64p), ("xi_under_over", _u64p), ("work_hist", _dp)] +
+                [("turn_on", _dp), ("G", _dp), ("G_se", _dp), ("xi_hist_free", _u64p)])
 
 
 class ppp_timings(ctypes.Structure):
@@ -195,7 +202,8 @@ def make_problem(prob: dict):
     p.xi_min = float(prob["xi_min"]); p.xi_bin = float(prob["xi_bin"]); p.xi_nbins = int(prob["xi_nbins"])
     p.w_bin = float(prob.get("w_bin", 0.01)); p.w_half_bins = int(prob.get("w_half_bins", 0))
     p.n_jack_blocks = int(prob.get("n_blocks", 0)); p.xi_bound = float(prob.get("xi_bound", 1.0e4))
-    p.flags = int(prob.get("flags", 0)) | (PPP_FLAG_SEQUENTIAL if prob.get("sequential", False) else 0)
+    p.flags = (int(prob.get("flags", 0)) | (PPP_FLAG_SEQUENTIAL if prob.get("sequential", False) else 0) |
+               (PPP_FLAG_FREE_ENSEMBLE if prob.get("free_ensemble", False) else 0))
     return p, (lam, init)
 
 
@@ -271,6 +279,10 @@ def _result_buffers(prob):
         bufs["work_hist"] = np.zeros((s, 2 * M + 1)); r.work_hist = bufs["work_hist"].ctypes.data_as(_dp)
     else:
         r.work_hist = None
+    bufs["turn_on_raw"] = np.full(len(TURN_ON_FIELDS), np.nan); r.turn_on = bufs["turn_on_raw"].ctypes.data_as(_dp)
+    for n in ("G", "G_se"):
+        bufs[n] = np.full(s, np.nan); setattr(r, n, bufs[n].ctypes.data_as(_dp))
+    bufs["xi_hist_free"] = np.zeros(K, dtype=np.uint64); r.xi_hist_free = bufs["xi_hist_free"].ctypes.data_as(_u64p)
     return r, bufs
 
 
@@ -282,6 +294,7 @@ def ppp_get_result(h, prob, index=None):
     else:
         st = _check(lib().ppp_batch_get_result(h, int(index), ctypes.byref(r)), h, "ppp_batch_get_result")
     bufs["status"] = st
+    bufs["turn_on"] = dict(zip(TURN_ON_FIELDS, (float(v) for v in bufs.pop("turn_on_raw"))))
     return bufs
 
 

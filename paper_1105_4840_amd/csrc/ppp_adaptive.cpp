@@ -127,7 +127,8 @@ ppp_status ppp_mlp_adam(float *d_params, const float *d_grad, float *d_m, float 
 
 ppp_status ppp_adaptive_workspace_size(const ppp_problem *base, const ppp_adaptive *a, size_t *bytes) {
     if (!bytes || !valid_adaptive(base, a)) return PPP_E_INVALID_ARG;
-    if (base->flags & PPP_FLAG_SEQUENTIAL) return PPP_E_UNSUPPORTED;   // placement runs the parallel protocol
+    // placement runs the parallel protocol on restrained windows only
+    if (base->flags & (PPP_FLAG_SEQUENTIAL | PPP_FLAG_FREE_ENSEMBLE)) return PPP_E_UNSUPPORTED;
     // the largest run: max_windows windows with the production replica count
     std::vector<double> lam(a->max_windows);
     const double lo = base->lambda[0], hi = base->lambda[base->n_windows - 1];

@@ -17,6 +17,10 @@ enum AccField : int {
     A_MF2, A_SF2, // same for 2a
     A_MR, A_SR,   // reverse perturbation lambda_i -> lambda_{i-1}
     A_MR2, A_SR2,
+    // With the free ensemble (index s) the ends are perturbed toward it as well:
+    // window 1's reverse and window s's forward entries hold a = +beta k/2 d^2
+    // (Eq. 5); the free ensemble's forward and reverse entries hold
+    // a = -beta k/2 (xi - lambda_1)^2 and -beta k/2 (xi - lambda_s)^2 (Eq. 6).
     A_UNDER, A_OVER,
     A_BLOWN,      // 1 if the replica was frozen
     A_NFIELDS
@@ -31,11 +35,15 @@ enum OutField : int {
     O_N_SAMPLES, O_N_BLOWN, O_UNDER, O_OVER,
     O_KISH, O_OVL, O_DL_SIGMA, O_DL_REACH, O_CRIT,
     O_DF_FLUCT_LIT, O_DF_GAUSS_LIT, O_DF_JE_HIST_LIT,
+    O_G, O_G_SE,            // Eq. 15, with the free ensemble only
     O_NFIELDS
 };
 
-// Jackknife leave-one-out profiles stored per block: JE, fluct, gauss, com.
-constexpr int JK_FIELDS = 4;
+// Jackknife leave-one-out profiles stored per block: JE, fluct, gauss, com, G.
+constexpr int JK_FIELDS = 5;
+// Leave-one-out turn-on values per block: Eq. 5 and Eq. 6 at lambda_1 and
+// lambda_s, and the Eq. 10 log-average.
+constexpr int JK_TURN = 5;
 
 struct DevProblem {
     // model
@@ -48,6 +56,8 @@ struct DevProblem {
     int32_t sample_every;
     int32_t variant_lanes, variant_beads;   // chain kernel shape (G lanes x B beads per lane)
     int32_t sequential;     // 1: sequential pulling protocol (windows one after another per replica)
+    int32_t free_ens;       // 1: the unrestrained ensemble runs as window index s (k = 0)
+    int32_t n_sim_windows;  // s + free_ens: windows with replicas, records and histograms
     int64_t n_steps, n_equil, n_pull;
     uint64_t seed;
     double k, kT, beta, dt;
@@ -61,15 +71,18 @@ struct DevProblem {
     double fix_x, fix_y, fix_z;              // fixed bead 0
     double pad_z0, pad_dz;                   // where padding beads are parked
     // byte offsets of this problem's arrays inside the workspace
-    int64_t off_lambda;     // double [s]
+    // S = n_sim_windows; the free ensemble's lambda entry is lambda_1
+    int64_t off_lambda;     // double [S]
     int64_t off_init;       // double [3 N] (chain) or [1]
-    int64_t off_state;      // T [s R][6][n_pad] (chain) or T [s R][2] (1-D: x, eta)
-    int64_t off_acc;        // double [s R][A_NFIELDS]
-    int64_t off_hist;       // u64 [s][K]
-    int64_t off_blk;        // double [s][B][A_NFIELDS]
-    int64_t off_tot;        // double [s][A_NFIELDS]
+    int64_t off_state;      // T [S R][6][n_pad] (chain) or T [S R][2] (1-D: x, eta)
+    int64_t off_acc;        // double [S R][A_NFIELDS]
+    int64_t off_hist;       // u64 [S][K]
+    int64_t off_blk;        // double [S][B][A_NFIELDS]
+    int64_t off_tot;        // double [S][A_NFIELDS]
     int64_t off_jack;       // double [B][JK_FIELDS][s]
+    int64_t off_jack_turn;  // double [B][JK_TURN]
     int64_t off_out;        // double [O_NFIELDS][s]
+    int64_t off_turn;       // double [PPP_ON_NFIELDS]
     // App. C in two chains: 0 the primary reading, 1 the paper's listing as printed
     int64_t off_pairs_shift;// int32 [2][s][K] (chain 1: floor of the work in bins)
     int64_t off_pairs_ceil; // int32 [s][K] (chain 1: its ceiling)

@@ -13,6 +13,7 @@
 //                       the variance formula of Sec. IV A.
 #include <hip/hip_runtime.h>
 
+#include "ppp.h"
 #include "ppp_device.hpp"
 #include "ppp_launch.hpp"
 
@@ -26,7 +27,7 @@ __global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ 
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
-    const int64_t nh = (int64_t)P.n_windows * P.xi_nbins;
+    const int64_t nh = (int64_t)P.n_sim_windows * P.xi_nbins;
     for (int64_t i = tid; i < nh; i += stride) hist[i] = 0ull;
     if (P.w_half_bins > 0) {
         double *om = dptr(ws, P.off_omega);
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(64) void k_reduce_blocks(const DevProblem *__restri
     const DevProblem &P = probs[blockIdx.y];
     const int B = P.n_blocks, R = P.n_replicas;
     const int wb = blockIdx.x;
-    if (wb >= P.n_windows * B) return;
+    if (wb >= P.n_sim_windows * B) return;
     const int w = wb / B, b = wb % B;
     const int lo = (int)(((int64_t)b * R + B - 1) / B);
     const int hi = (int)(((int64_t)(b + 1) * R + B - 1) / B);
@@ -108,6 +109,26 @@ __device__ __forceinline__ void step_terms(const DevProblem &P, const WinStat &s
     ga = fl + 0.5 * P.k * dl * dl * (1.0 - gamma2);
 }
 
+// Turn-on free energies from the records of window 1 (a1), window s (as) and
+// the unrestrained ensemble (a0); je_s = dF^JE(lambda_s) from the same records.
+struct TurnOn {
+    double eq5_first, eq6_first, eq5_last, eq6_last, eq10;
+};
+__device__ __forceinline__ TurnOn turn_on(const DevProblem &P, const double *a1, const double *as, const double *a0,
+                                          double je_s) {
+    TurnOn r;
+    // Eq. 5: DF = kT ln <exp(+beta k/2 (x - lambda)^2)> over the restrained window
+    r.eq5_first = P.kT * (lse_value(a1[A_MR], a1[A_SR]) - log(a1[A_N]));
+    r.eq5_last = P.kT * (lse_value(as[A_MF], as[A_SF]) - log(as[A_N]));
+    // Eq. 6: DF = -kT ln <exp(-beta k/2 (x_0 - lambda)^2)> over the free ensemble
+    r.eq6_first = -P.kT * (lse_value(a0[A_MF], a0[A_SF]) - log(a0[A_N]));
+    r.eq6_last = -P.kT * (lse_value(a0[A_MR], a0[A_SR]) - log(a0[A_N]));
+    // Eq. 10 factorised over x_0, x_1 .. x_s: the turn-on at lambda_1 from x_0, the
+    // steps, and the turn-off at lambda_s from x_s
+    r.eq10 = -P.beta * (r.eq6_first + je_s - r.eq5_last);
+    return r;
+}
+
 __device__ double block_sum(double v, double *sh) {
     const int t = threadIdx.x;
     sh[t] = v;
@@ -134,8 +155,9 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
     const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist);
 #define OUT(f, i) out[(int64_t)(f) * s + (i)]
 
+    const int S = P.n_sim_windows;
     // (a) window totals: blocks merged in block order
-    for (int w = t; w < s; w += blockDim.x) {
+    for (int w = t; w < S; w += blockDim.x) {
         double a[A_NFIELDS];
         acc_empty(a);
         for (int b = 0; b < B; ++b) acc_merge(a, blk + ((int64_t)w * B + b) * A_NFIELDS);
@@ -195,6 +217,33 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
             OUT(O_DF_COM, j) = 0.5 * (OUT(O_DF_JE, j) + OUT(O_DF_FLUCT, j));
             OUT(O_DF_UNC, j) = 0.5 * (OUT(O_DF_JE, j) - OUT(O_DF_FLUCT, j));
         }
+        double *turn = dptr(ws, P.off_turn);
+        if (P.free_ens) {
+            const double *a1 = tot, *as = tot + (int64_t)(s - 1) * A_NFIELDS, *a0 = tot + (int64_t)s * A_NFIELDS;
+            const TurnOn on = turn_on(P, a1, as, a0, OUT(O_DF_JE, s - 1));
+            turn[PPP_ON_EQ5_FIRST] = on.eq5_first;
+            turn[PPP_ON_EQ6_FIRST] = on.eq6_first;
+            turn[PPP_ON_EQ5_LAST] = on.eq5_last;
+            turn[PPP_ON_EQ6_LAST] = on.eq6_last;
+            turn[PPP_ON_EQ10_LOG] = on.eq10;
+            // Eq. 7: <k/2 (x - lambda)^2> over the restrained window and over x_0
+            const double dls = lam[s - 1] - lam[0];
+            turn[PPP_ON_LOWER_FIRST] = 0.5 * P.k * a1[A_S2] / a1[A_N];
+            turn[PPP_ON_UPPER_FIRST] = 0.5 * P.k * a0[A_S2] / a0[A_N];
+            turn[PPP_ON_LOWER_LAST] = 0.5 * P.k * as[A_S2] / as[A_N];
+            turn[PPP_ON_UPPER_LAST] = 0.5 * P.k * (a0[A_S2] - 2.0 * dls * a0[A_S1] + a0[A_N] * dls * dls) / a0[A_N];
+            const WinStat f0 = win_stat(a0, lam[0]);
+            turn[PPP_ON_FREE_N] = a0[A_N];
+            turn[PPP_ON_FREE_BLOWN] = a0[A_BLOWN];
+            turn[PPP_ON_FREE_MEAN] = f0.mean;
+            turn[PPP_ON_FREE_STD] = sqrt(f0.var);
+            turn[PPP_ON_FREE_UNDER] = a0[A_UNDER];
+            turn[PPP_ON_FREE_OVER] = a0[A_OVER];
+            for (int j = 0; j < s; ++j) OUT(O_G, j) = OUT(O_DF_JE, j) - on.eq5_first;   // Eq. 15
+        } else {
+            for (int f = 0; f < PPP_ON_NFIELDS; ++f) turn[f] = NAN;
+            for (int j = 0; j < s; ++j) OUT(O_G, j) = NAN;
+        }
     }
     // (d) jackknife: block b removed from every window
     if (B > 1) {
@@ -202,22 +251,60 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
             double je = 0, fl = 0, ga = 0;
             double *jb = jack + (int64_t)b * JK_FIELDS * s;
             jb[0 * s] = 0; jb[1 * s] = 0; jb[2 * s] = 0; jb[3 * s] = 0;
-            for (int j = 1; j < s; ++j) {
-                double a[A_NFIELDS];
+            // window w without block b
+            auto loo = [&](int w, double *a) {
                 acc_empty(a);
                 for (int c = 0; c < B; ++c)
-                    if (c != b) acc_merge(a, blk + ((int64_t)(j - 1) * B + c) * A_NFIELDS);
+                    if (c != b) acc_merge(a, blk + ((int64_t)w * B + c) * A_NFIELDS);
+            };
+            double a1[A_NFIELDS];
+            for (int j = 1; j < s; ++j) {
+                double a[A_NFIELDS];
+                loo(j - 1, a);
+                if (j == 1) for (int f = 0; f < A_NFIELDS; ++f) a1[f] = a[f];
                 const WinStat st = win_stat(a, lam[j - 1]);
                 double dje, dfl, dga;
                 step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
                 je += dje; fl += dfl; ga += dga;
                 jb[0 * s + j] = je; jb[1 * s + j] = fl; jb[2 * s + j] = ga; jb[3 * s + j] = 0.5 * (je + fl);
             }
+            if (P.free_ens) {
+                double as[A_NFIELDS], a0[A_NFIELDS];
+                loo(s - 1, as);
+                loo(s, a0);
+                const TurnOn on = turn_on(P, a1, as, a0, je);
+                double *jt = dptr(ws, P.off_jack_turn) + (int64_t)b * JK_TURN;
+                jt[0] = on.eq5_first; jt[1] = on.eq6_first; jt[2] = on.eq5_last; jt[3] = on.eq6_last; jt[4] = on.eq10;
+                for (int j = 0; j < s; ++j) jb[4 * s + j] = jb[0 * s + j] - on.eq5_first;
+            } else {
+                for (int j = 0; j < s; ++j) jb[4 * s + j] = NAN;
+            }
         }
     }
     __syncthreads();
+    if (t == 0 && P.free_ens) {
+        const int fields[JK_TURN] = {PPP_ON_EQ5_FIRST_SE, PPP_ON_EQ6_FIRST_SE, PPP_ON_EQ5_LAST_SE,
+                                     PPP_ON_EQ6_LAST_SE, PPP_ON_EQ10_LOG_SE};
+        const double *jt = dptr(ws, P.off_jack_turn);
+        double *turn = dptr(ws, P.off_turn);
+        for (int q = 0; q < JK_TURN; ++q) {
+            double se = NAN;
+            if (B > 1) {
+                double m = 0;
+                for (int b = 0; b < B; ++b) m += jt[b * JK_TURN + q];
+                m /= B;
+                double ss = 0;
+                for (int b = 0; b < B; ++b) {
+                    const double d = jt[b * JK_TURN + q] - m;
+                    ss += d * d;
+                }
+                se = sqrt((B - 1.0) / B * ss);
+            }
+            turn[fields[q]] = se;
+        }
+    }
     for (int j = t; j < s; j += blockDim.x) {
-        const int fields[JK_FIELDS] = {O_DF_JE_SE, O_DF_FLUCT_SE, O_DF_GAUSS_SE, O_DF_COM_SE};
+        const int fields[JK_FIELDS] = {O_DF_JE_SE, O_DF_FLUCT_SE, O_DF_GAUSS_SE, O_DF_COM_SE, O_G_SE};
         for (int q = 0; q < JK_FIELDS; ++q) {
             double se = NAN;
             if (B > 1) {

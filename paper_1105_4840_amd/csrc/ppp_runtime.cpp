@@ -124,7 +124,8 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
     if (!finite_pos(p->kT)) { msg = "kT must be > 0"; return PPP_E_INVALID_ARG; }
     if (!finite_pos(p->dt)) { msg = "dt must be > 0"; return PPP_E_INVALID_ARG; }
     if (p->n_replicas < 1) { msg = "n_replicas must be >= 1"; return PPP_E_INVALID_ARG; }
-    if ((int64_t)p->n_windows * p->n_replicas > 0x7fffffffLL) { msg = "too many replicas"; return PPP_E_INVALID_ARG; }
+    const int64_t sim_windows = (int64_t)p->n_windows + ((p->flags & PPP_FLAG_FREE_ENSEMBLE) ? 1 : 0);
+    if (sim_windows * p->n_replicas > 0x7fffffffLL) { msg = "too many replicas"; return PPP_E_INVALID_ARG; }
     if (p->sample_every < 1) { msg = "sample_every must be >= 1"; return PPP_E_INVALID_ARG; }
     if (p->n_steps < 1 || p->n_steps > 0xffffffffLL) { msg = "n_steps must be in [1, 2^32)"; return PPP_E_INVALID_ARG; }
     if (p->n_equil < 0 || p->n_equil >= p->n_steps) { msg = "need 0 <= n_equil < n_steps"; return PPP_E_INVALID_ARG; }
@@ -134,9 +135,12 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
     if (p->w_half_bins < 0 || p->w_half_bins > 50000000) { msg = "w_half_bins out of range"; return PPP_E_INVALID_ARG; }
     if (p->w_half_bins > 0 && !finite_pos(p->w_bin)) { msg = "w_bin must be > 0"; return PPP_E_INVALID_ARG; }
     if (p->n_jack_blocks < 0 || p->n_jack_blocks > 4096) { msg = "n_jack_blocks must be in [0, 4096]"; return PPP_E_INVALID_ARG; }
-    if ((p->flags & ~PPP_FLAG_SEQUENTIAL) != 0) { msg = "unknown flags"; return PPP_E_INVALID_ARG; }
+    if ((p->flags & ~(PPP_FLAG_SEQUENTIAL | PPP_FLAG_FREE_ENSEMBLE)) != 0) { msg = "unknown flags"; return PPP_E_INVALID_ARG; }
     if ((p->flags & PPP_FLAG_SEQUENTIAL) && (int64_t)p->n_windows * p->n_steps > 0xffffffffLL) {
         msg = "a sequential run must have fewer than 2^32 steps per replica"; return PPP_E_INVALID_ARG;
+    }
+    if ((p->flags & PPP_FLAG_SEQUENTIAL) && (p->flags & PPP_FLAG_FREE_ENSEMBLE)) {
+        msg = "the free ensemble runs with the parallel protocol only"; return PPP_E_UNSUPPORTED;
     }
     if (p->precision != PPP_FP32_FORCES && p->precision != PPP_FP64) { msg = "unknown precision"; return PPP_E_INVALID_ARG; }
     if (p->model == PPP_MODEL_1D) {
@@ -221,6 +225,8 @@ ppp_status build_problem(const ppp_problem *p, ProblemHost &ph, const std::vecto
     if (st != PPP_OK) return st;
     ph.p = *p;
     ph.lambda.assign(p->lambda, p->lambda + p->n_windows);
+    // the unrestrained ensemble's entry: its xi is recorded relative to lambda_1
+    if (p->flags & PPP_FLAG_FREE_ENSEMBLE) ph.lambda.push_back(p->lambda[0]);
     ph.p.lambda = ph.lambda.data();
     const bool chain = p->model == PPP_MODEL_CHAIN;
     if (chain) {
@@ -254,6 +260,8 @@ ppp_status build_problem(const ppp_problem *p, ProblemHost &ph, const std::vecto
     d.variant_beads = ph.B;
     d.n_steps = p->n_steps;
     d.sequential = (p->flags & PPP_FLAG_SEQUENTIAL) ? 1 : 0;
+    d.free_ens = (p->flags & PPP_FLAG_FREE_ENSEMBLE) ? 1 : 0;
+    d.n_sim_windows = d.n_windows + d.free_ens;
     d.n_equil = p->n_equil;
     d.n_pull = p->n_pull;
     d.seed = p->seed;
@@ -290,19 +298,21 @@ ppp_status build_problem(const ppp_problem *p, ProblemHost &ph, const std::vecto
 // Byte layout of the problem's arrays from offset `at`; returns the end.
 int64_t layout_problem(ProblemHost &ph, int64_t at) {
     DevProblem &d = ph.dev;
-    const int64_t s = d.n_windows, R = d.n_replicas, K = d.xi_nbins, Bk = d.n_blocks;
+    const int64_t s = d.n_windows, S = d.n_sim_windows, R = d.n_replicas, K = d.xi_nbins, Bk = d.n_blocks;
     const int64_t tsize = d.precision == PPP_FP64 ? 8 : 4;
     ph.region_begin = at;
     auto take = [&](int64_t bytes) { const int64_t o = at; at = align_up(at + std::max<int64_t>(bytes, 1)); return o; };
-    d.off_lambda = take(s * 8);
+    d.off_lambda = take(S * 8);
     d.off_init = take((int64_t)ph.init.size() * 8);
-    d.off_state = take(d.model == PPP_MODEL_CHAIN ? s * R * 6 * d.n_pad * tsize : s * R * 2 * tsize);
-    d.off_acc = take(s * R * A_NFIELDS * 8);
-    d.off_hist = take(s * K * 8);
-    d.off_blk = take(s * Bk * A_NFIELDS * 8);
-    d.off_tot = take(s * A_NFIELDS * 8);
+    d.off_state = take(d.model == PPP_MODEL_CHAIN ? S * R * 6 * d.n_pad * tsize : S * R * 2 * tsize);
+    d.off_acc = take(S * R * A_NFIELDS * 8);
+    d.off_hist = take(S * K * 8);
+    d.off_blk = take(S * Bk * A_NFIELDS * 8);
+    d.off_tot = take(S * A_NFIELDS * 8);
     d.off_jack = take(Bk * JK_FIELDS * s * 8);
+    d.off_jack_turn = take(Bk * JK_TURN * 8);
     d.off_out = take((int64_t)O_NFIELDS * s * 8);
+    d.off_turn = take(PPP_ON_NFIELDS * 8);
     if (d.w_half_bins > 0) {
         d.off_pairs_shift = take(2 * s * K * 4);
         d.off_pairs_ceil = take(s * K * 4);
@@ -329,7 +339,7 @@ int reps_per_item(const ProblemHost &ph) { return ph.dev.model == PPP_MODEL_CHAI
 // windows one item touches still fits in LDS.
 void make_items(ProblemHost &ph, int prob_index, std::vector<WorkItem> &items, bool allow_span) {
     const int per = reps_per_item(ph);
-    const int64_t R = ph.dev.n_replicas, total = (int64_t)ph.dev.n_windows * R;
+    const int64_t R = ph.dev.n_replicas, total = (int64_t)ph.dev.n_sim_windows * R;
     ph.first_item = (int)items.size();
     ph.item_windows = 1;
     const int64_t span_windows = (per - 1) / R + 2;   // a run of `per` replicas touches at most this many
@@ -346,7 +356,7 @@ void make_items(ProblemHost &ph, int prob_index, std::vector<WorkItem> &items, b
             ph.item_windows = std::max(ph.item_windows, (int)((g + n - 1) / R - g / R + 1));
         }
     } else {
-        for (int w = 0; w < ph.dev.n_windows; ++w)
+        for (int w = 0; w < ph.dev.n_sim_windows; ++w)
             for (int r = 0; r < ph.dev.n_replicas; r += per)
                 items.push_back(WorkItem{prob_index, w, r, std::min(per, ph.dev.n_replicas - r)});
     }
@@ -361,7 +371,7 @@ void finish_layout(ppp_handle *h) {
     h->max_windows = h->max_blocks = h->max_k = h->max_m = 0;
     for (auto &ph : h->probs) {
         at = layout_problem(ph, at);
-        h->max_windows = std::max(h->max_windows, ph.dev.n_windows);
+        h->max_windows = std::max(h->max_windows, ph.dev.n_sim_windows);
         h->max_blocks = std::max(h->max_blocks, ph.dev.n_blocks);
         h->max_k = std::max(h->max_k, ph.dev.xi_nbins);
         h->max_m = std::max(h->max_m, ph.dev.w_half_bins);
@@ -492,9 +502,21 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
     if (out->work_hist) {
         if (appc) HIPCHK(h, hipMemcpy(out->work_hist, h->ws + d.off_omega, s * (2 * (int64_t)d.w_half_bins + 1) * 8, hipMemcpyDeviceToHost));
     }
-    // more than 1% of some window's replicas frozen?
+    // the turn-on outputs (Eqs. 5-7, 10, 15)
+    std::vector<double> turn(PPP_ON_NFIELDS, NAN);
+    if (d.free_ens) HIPCHK(h, hipMemcpy(turn.data(), h->ws + d.off_turn, PPP_ON_NFIELDS * 8, hipMemcpyDeviceToHost));
+    put(out->turn_on, turn, 0, PPP_ON_NFIELDS);
+    put(out->G, o, F(O_G), s);
+    put(out->G_se, o, F(O_G_SE), s);
+    if (out->xi_hist_free) {
+        if (d.free_ens) HIPCHK(h, hipMemcpy(out->xi_hist_free, h->ws + d.off_hist + s * K * 8, K * 8, hipMemcpyDeviceToHost));
+        else std::memset(out->xi_hist_free, 0, K * 8);
+    }
+    // more than 1% of some window's replicas (the free ensemble's included) frozen?
     for (int64_t i = 0; i < s; ++i)
         if (o[F(O_N_BLOWN) + i] > 0.01 * d.n_replicas) return fail(h, PPP_E_NUMERICAL, "more than 1% of the replicas of a window were frozen");
+    if (d.free_ens && turn[PPP_ON_FREE_BLOWN] > 0.01 * d.n_replicas)
+        return fail(h, PPP_E_NUMERICAL, "more than 1% of the replicas of the free ensemble were frozen");
     return PPP_OK;
 }
 
@@ -791,7 +813,7 @@ ppp_status ppp_get_timings(const ppp_handle *hc, ppp_timings *out) {
     int64_t rs = 0;
     for (auto &ph : h->probs)
         rs += ph.dev.sequential ? (int64_t)ph.dev.n_replicas * std::min(total_steps(ph), h->steps_done)
-                                : (int64_t)ph.dev.n_windows * ph.dev.n_replicas * std::min(ph.dev.n_steps, h->steps_done);
+                                : (int64_t)ph.dev.n_sim_windows * ph.dev.n_replicas * std::min(ph.dev.n_steps, h->steps_done);
     out->replica_steps = rs;
     out->sim_launches = h->sim_launches;
     out->variant_lanes = h->probs[0].G;
@@ -806,7 +828,7 @@ ppp_status ppp_checkpoint(ppp_handle *h, void *host_buf, size_t *bytes) {
     if (!h || !bytes) return PPP_E_INVALID_ARG;
     if (h->batch) return fail(h, PPP_E_UNSUPPORTED, "checkpoint of batched handles");
     size_t need = 16;
-    for (auto &ph : h->probs) need += (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
+    for (auto &ph : h->probs) need += (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_sim_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
     if (!host_buf) { *bytes = need; return PPP_OK; }
     if (*bytes < need) return fail(h, PPP_E_INVALID_ARG, "checkpoint buffer too small");
     if (!h->begun) return fail(h, PPP_E_STATE, "nothing to checkpoint");
@@ -816,7 +838,7 @@ ppp_status ppp_checkpoint(ppp_handle *h, void *host_buf, size_t *bytes) {
     std::memcpy(p + 8, &h->steps_done, 8);
     size_t at = 16;
     for (auto &ph : h->probs) {
-        const size_t n = (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
+        const size_t n = (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_sim_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
         HIPCHK(h, hipMemcpy(p + at, h->ws + ph.dev.off_state, n, hipMemcpyDeviceToHost));
         at += n;
     }
@@ -828,7 +850,7 @@ ppp_status ppp_restore(ppp_handle *h, void *ws, size_t ws_bytes, const void *hos
     if (!h || !host_buf) return PPP_E_INVALID_ARG;
     if (h->batch) return fail(h, PPP_E_UNSUPPORTED, "restore of batched handles");
     size_t need = 16;
-    for (auto &ph : h->probs) need += (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
+    for (auto &ph : h->probs) need += (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_sim_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
     if (bytes != need) return fail(h, PPP_E_INVALID_ARG, "checkpoint size does not match this problem");
     const char *p = static_cast<const char *>(host_buf);
     uint64_t magic;
@@ -846,7 +868,7 @@ ppp_status ppp_restore(ppp_handle *h, void *ws, size_t ws_bytes, const void *hos
                           reinterpret_cast<int *>(h->ws + h->off_tickets), 64, st));
     size_t at = 16;
     for (auto &ph : h->probs) {
-        const size_t n = (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
+        const size_t n = (size_t)(ph.dev.off_hist + (int64_t)ph.dev.n_sim_windows * ph.dev.xi_nbins * 8 - ph.dev.off_state);
         HIPCHK(h, hipMemcpyAsync(h->ws + ph.dev.off_state, p + at, n, hipMemcpyHostToDevice, st));
         at += n;
     }

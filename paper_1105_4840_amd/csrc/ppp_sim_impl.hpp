@@ -62,18 +62,38 @@ __device__ __forceinline__ void accumulate(const DevProblem &P, const double *la
     acc[A_S2] += d * d;
     acc[A_XMIN] = fmin(acc[A_XMIN], xi);
     acc[A_XMAX] = fmax(acc[A_XMAX], xi);
-    if (w + 1 < s) {
-        // a = -beta k/2 [(xi - lambda_{i+1})^2 - (xi - lambda_i)^2] = beta k dl (d - dl/2)
-        const double dl = lam[w + 1] - lam[w];
-        const double a = P.beta * P.k * dl * (d - 0.5 * dl);
-        lse_push(acc[A_MF], acc[A_SF], a);
-        lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
-    }
-    if (w > 0) {
-        const double dl = lam[w - 1] - lam[w];
-        const double a = P.beta * P.k * dl * (d - 0.5 * dl);
-        lse_push(acc[A_MR], acc[A_SR], a);
-        lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
+    if (w == s) {
+        // the unrestrained ensemble (d = xi - lambda_1): switching the restraint on
+        // at lambda_1 or at lambda_s costs W_H = k/2 (x_0 - lambda)^2 (Eqs. 4, 6)
+        const double e = xi - lam[s - 1];
+        const double af = -0.5 * P.beta * P.k * d * d, ar = -0.5 * P.beta * P.k * e * e;
+        lse_push(acc[A_MF], acc[A_SF], af);
+        lse_push(acc[A_MF2], acc[A_SF2], 2.0 * af);
+        lse_push(acc[A_MR], acc[A_SR], ar);
+        lse_push(acc[A_MR2], acc[A_SR2], 2.0 * ar);
+    } else {
+        if (w + 1 < s) {
+            // a = -beta k/2 [(xi - lambda_{i+1})^2 - (xi - lambda_i)^2] = beta k dl (d - dl/2)
+            const double dl = lam[w + 1] - lam[w];
+            const double a = P.beta * P.k * dl * (d - 0.5 * dl);
+            lse_push(acc[A_MF], acc[A_SF], a);
+            lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
+        } else if (P.free_ens) {
+            // switching the restraint at lambda_s off: a = +beta k/2 d^2 (Eq. 5)
+            const double a = 0.5 * P.beta * P.k * d * d;
+            lse_push(acc[A_MF], acc[A_SF], a);
+            lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
+        }
+        if (w > 0) {
+            const double dl = lam[w - 1] - lam[w];
+            const double a = P.beta * P.k * dl * (d - 0.5 * dl);
+            lse_push(acc[A_MR], acc[A_SR], a);
+            lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
+        } else if (P.free_ens) {
+            const double a = 0.5 * P.beta * P.k * d * d;   // the same at lambda_1 (Eq. 5)
+            lse_push(acc[A_MR], acc[A_SR], a);
+            lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
+        }
     }
     const double fb = floor((xi - P.xi_min) / P.xi_bin);
     if (fb < 0.0) acc[A_UNDER] += 1.0;
@@ -116,12 +136,15 @@ template <typename T> __device__ __forceinline__ T *state_ptr(char *ws, const De
 // eta_n is component n mod 4 of the Philox block with counter (gid, n div 4, 0, 0).
 // ===========================================================================
 template <typename T>
-__device__ __forceinline__ T force_1d(const DevProblem &P, T x, T centre) {
+__device__ __forceinline__ T force_1d(const DevProblem &P, T x, T centre, T kr) {
     T f;
     if (P.pot_kind == 0) f = (T)(-4.0 * P.pot_a) * x * (x * x - (T)P.pot_b);
     else f = (T)(-P.pot_kappa) * x;
-    return f - (T)P.k * (x - centre);
+    return f - kr * (x - centre);
 }
+
+// Restraint stiffness of window w: k, or 0 for the unrestrained ensemble (w = s).
+__device__ __forceinline__ double window_k(const DevProblem &P, int w) { return w < P.n_windows ? P.k : 0.0; }
 
 template <typename T>
 __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkItem &item, int w, int rep, char *ws,
@@ -162,6 +185,7 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
     }
     const bool record = traj != nullptr && g == traj_rep;
     if (record && step_begin == 0) traj[0] = (double)x;
+    const T kr = (T)window_k(P, w);
     const T mu_dt = (T)(P.mobility * P.dt);
     const T amp = P.integrator_1d == 0 ? (T)sqrt(0.5 * P.mobility * P.kT * P.dt)
                                        : (T)sqrt(2.0 * P.mobility * P.kT * P.dt);
@@ -170,7 +194,7 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
     uint32_t zblock = 0xFFFFFFFFu;
     int64_t n_sample = s0 + next_sample_after(P, step_begin - s0);
     for (int64_t n = step_begin + 1; n <= n_end && alive; ++n) {
-        const T F = force_1d<T>(P, x, (T)(w == 0 || !P.sequential ? centre_at(P, lam_w, n - 1) : lam_w));
+        const T F = force_1d<T>(P, x, (T)(w == 0 || !P.sequential ? centre_at(P, lam_w, n - 1) : lam_w), kr);
         const uint32_t blk = (uint32_t)(n >> 2);
         if (blk != zblock) { Normal4<T>::get(P.seed, gid, blk, 0u, 0u, z); zblock = blk; }
         const T eta = z[n & 3];
@@ -242,11 +266,11 @@ struct ChainForce {
         }
     }
 
-    // Forces on the owned beads at restraint centre `centre`.  lane g of group base `gbase`;
-    // an idle lane (beyond the wavefront's last whole group: gbase + G > 64) only
-    // exchanges data with itself.
+    // Forces on the owned beads with the restraint kr/2 (xi - centre)^2.  lane g of
+    // group base `gbase`; an idle lane (beyond the wavefront's last whole group:
+    // gbase + G > 64) only exchanges data with itself.
     // e[0..3] = bond, angle, lj, restraint energy contributions of this lane (ENERGY only).
-    __device__ __forceinline__ static void compute(const DevProblem &P, int g, int gbase, T centre,
+    __device__ __forceinline__ static void compute(const DevProblem &P, int g, int gbase, T centre, T kr,
                                                    const T (&px)[B], const T (&py)[B], const T (&pz)[B],
                                                    T (&fx)[B], T (&fy)[B], T (&fz)[B], double *e) {
         const int N = P.n_beads;
@@ -414,9 +438,9 @@ struct ChainForce {
                 T xi, ux, uy, uz;
                 if (P.rc_mode == 1) { xi = dz; ux = 0; uy = 0; uz = 1; }
                 else { T ixi; len_inv(dx * dx + dy * dy + dz * dz, xi, ixi); ux = dx * ixi; uy = dy * ixi; uz = dz * ixi; }
-                const T fr = -(T)P.k * (xi - centre);
+                const T fr = -kr * (xi - centre);
                 fx[b] += fr * ux; fy[b] += fr * uy; fz[b] += fr * uz;
-                if (ENERGY) e_res += 0.5 * P.k * (double)(xi - centre) * (double)(xi - centre);
+                if (ENERGY) e_res += 0.5 * (double)kr * (double)(xi - centre) * (double)(xi - centre);
             }
         }
         if (ENERGY) { e[0] = e_bond; e[1] = e_ang; e[2] = e_lj; e[3] = e_res; }
@@ -461,6 +485,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     const double lam_w = lam[w];
     const int64_t n_end = step_end < s0 + P.n_steps ? step_end : s0 + P.n_steps;
     auto centre = [&](int64_t n) { return stage == 0 ? centre_at(P, lam_w, n) : lam_w; };
+    const T kr = (T)window_k(P, w);
     const int i0 = g * B;
     const int last = N - 1;
     const int owner = last / B;       // lane (within group) owning the pulled end
@@ -509,7 +534,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     const uint64_t bal0 = __ballot(blown0 != 0);
     bool alive = active && ((bal0 >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1))) == 0ull;
 
-    ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(step_begin), px, py, pz, fx, fy, fz, nullptr);
+    ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(step_begin), kr, px, py, pz, fx, fy, fz, nullptr);
 
     const T h = (T)(0.5 * P.dt);
     const T c1 = (T)P.c1;
@@ -530,7 +555,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
             }
         }
-        ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(n), px, py, pz, fx, fy, fz, nullptr);
+        ChainForce<T, G, B, false>::compute(P, g, gbase, (T)centre(n), kr, px, py, pz, fx, fy, fz, nullptr);
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int i = i0 + b;
@@ -650,7 +675,7 @@ __global__ __launch_bounds__(WG) void chain_eval(const DevProblem *__restrict__ 
         else { px[b] = 0; py[b] = 0; pz[b] = (T)(P.pad_z0 + P.pad_dz * (i - N)); }
     }
     double e[4];
-    ChainForce<T, G, B, true>::compute(P, g, gbase, (T)centre, px, py, pz, fx, fy, fz, e);
+    ChainForce<T, G, B, true>::compute(P, g, gbase, (T)centre, (T)P.k, px, py, pz, fx, fy, fz, e);
     // group sums of the energy parts (fixed order over lanes)
     double tot[4];
     for (int q = 0; q < 4; ++q) {
@@ -681,7 +706,7 @@ __global__ void pot1d_eval(const DevProblem *__restrict__ probs, const double *_
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_rep) return;
     const T x = (T)coords[c];
-    forces[c] = (double)force_1d<T>(P, x, (T)centre);
+    forces[c] = (double)force_1d<T>(P, x, (T)centre, (T)P.k);
     double ho;
     if (P.pot_kind == 0) { const double q = (double)x * (double)x - P.pot_b; ho = P.pot_a * q * q; }
     else ho = 0.5 * P.pot_kappa * (double)x * (double)x;

@@ -53,7 +53,7 @@ def _status(prob):
     lambda p: p.update(w_bin=0.0),
     lambda p: p.update(n_blocks=10 ** 6),
     lambda p: p.update(n_blocks=-1),
-    lambda p: p.update(flags=2),
+    lambda p: p.update(flags=4),
     lambda p: p.update(flags=0x80000001),
     lambda p: p.update(sequential=True, n_steps=2 ** 31, n_equil=0),   # 21 x 2^31 steps per replica
     lambda p: p.update({"lambda": [0.0]}),
@@ -108,6 +108,33 @@ def test_sequential_protocol_accepted_where_supported():
         ppp.ppp_destroy(h)
     with pytest.raises(ppp.PppError):
         ppp.ppp_batch_create([p, dict(p)])
+
+
+def test_free_ensemble_accepted_where_supported():
+    """The unrestrained ensemble runs with the parallel protocol, batched too; not
+    with the sequential protocol nor for window placement."""
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    p["free_ensemble"] = True
+    assert _status(p) == 0
+    assert _status(dict(p, sequential=True)) == ppp.PPP_E_UNSUPPORTED
+    q = ppp_inputs.config_1d(n_replicas=8, n_steps=100)
+    q["free_ensemble"] = True
+    assert _status(q) == 0
+    h = ppp.ppp_batch_create([p, dict(p, n_beads=12)])
+    assert ppp.ppp_workspace_size(h) > 0
+    ppp.ppp_destroy(h)
+    # one more window of replicas, records and histogram in the workspace
+    h0, h1 = ppp.ppp_create(dict(p, free_ensemble=False)), ppp.ppp_create(p)
+    try:
+        assert ppp.ppp_workspace_size(h1) > ppp.ppp_workspace_size(h0)
+    finally:
+        ppp.ppp_destroy(h0); ppp.ppp_destroy(h1)
+    pb, keep = ppp.make_problem(p)
+    ad = ppp.ppp_adaptive(budget_replica_steps=10 ** 9, initial_windows=5, max_rounds=2, max_windows=16,
+                          target_dl_over_sigma=1.0, train_iters=10, lr=1e-3, init_seed=1, explore_replicas=8,
+                          explore_steps=100, min_production_steps=100)
+    n = ctypes.c_size_t()
+    assert ppp.lib().ppp_adaptive_workspace_size(ctypes.byref(pb), ctypes.byref(ad), ctypes.byref(n)) == ppp.PPP_E_UNSUPPORTED
 
 
 def test_error_strings():

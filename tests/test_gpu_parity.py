@@ -156,6 +156,21 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
         assert np.allclose(res["sigma_w"], ref["sigma_w"], rtol=1e-9, atol=1e-12)
         assert np.allclose(res["dF_je_var_paper"], ref["dF_je_var_paper"], rtol=1e-8, atol=1e-14)
         assert np.allclose(res["work_lost"], ref["work_lost"], atol=1e-12)
+    if prob.get("free_ensemble", False):
+        on, ron = res["turn_on"], ref["turn_on"]
+        for key in ("free_n", "free_blown", "free_under", "free_over"):
+            assert on[key] == ron[key], key
+        for key in ("eq5_first", "eq6_first", "eq5_last", "eq6_last", "eq10_log", "lower_first", "upper_first",
+                    "lower_last", "upper_last", "free_mean", "free_std"):
+            assert abs(on[key] - ron[key]) < prof_tol * (1 + abs(ron[key])), (key, on[key], ron[key])
+        for key in ("eq5_first_se", "eq6_first_se", "eq5_last_se", "eq6_last_se", "eq10_log_se"):
+            assert np.isclose(on[key], ron[key], rtol=1e-7, atol=1e-12, equal_nan=True), key
+        assert np.max(np.abs(res["G"] - ref["G"])) < prof_tol * (1 + np.max(np.abs(ref["G"])))
+        assert np.allclose(res["G_se"], ref["G_se"], rtol=1e-7, atol=1e-12, equal_nan=True)
+        assert np.array_equal(res["xi_hist_free"].astype(np.int64), ref["xi_hist_free"])
+    else:
+        assert all(np.isnan(v) for v in res["turn_on"].values())
+        assert np.all(np.isnan(res["G"])) and not np.any(res["xi_hist_free"])
 
 
 RUN_CASES = [
@@ -238,6 +253,46 @@ def test_run_without_samples():
     assert np.all(res["xi_hist"] == 0)
     for key in ("dF_je", "dF_fluct", "dF_gauss"):
         assert not np.any(np.isfinite(res[key][1:])) and not np.any(np.isfinite(ref[key][1:])), key
+
+
+def _free_case(name):
+    if name == "1d-harmonic":       # closed form exists; lambda range not symmetric about 0
+        p = ppp_inputs.config_harmonic_1d(kappa=4.0, k=2.0, n_replicas=70, n_steps=2000)
+        p["lambda"] = list(np.linspace(-1.0, 0.4, 8))
+        p["w_half_bins"] = 0
+    elif name == "1d-double-well":  # with App. C
+        p = ppp_inputs.config_1d(n_replicas=50, n_steps=2000, n_windows=6)
+        p.update({"k": 20.0, "w_half_bins": 2000})
+    elif name == "chain10":
+        p = ppp_inputs.config_chain_small(10, n_replicas=70, n_steps=600, n_windows=5, precision="fp64")
+        p.update({"w_half_bins": 3000, "w_bin": 0.05})
+    elif name == "chain32-pull":    # items span windows, the last one into the free ensemble
+        p = ppp_inputs.config_chain_small(32, n_replicas=21, n_steps=400, n_windows=3, precision="fp64")
+        p.update({"w_half_bins": 0, "n_pull": 100, "n_equil": 100})
+    else:
+        raise ValueError(name)
+    p["free_ensemble"] = True
+    return p
+
+
+@pytest.mark.parametrize("name", ["1d-harmonic", "1d-double-well", "chain10", "chain32-pull"])
+def test_free_ensemble_parity_fp64(name):
+    """Turn-on free energies (Eqs. 5-7, 10, 15) from the unrestrained ensemble run
+    as one more window: every output against the oracle, the per-window profiles
+    unchanged by it."""
+    _say(f"case free ensemble {name}")
+    prob = _free_case(name)
+    res, tim = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+    s, R = len(prob["lambda"]), prob["n_replicas"]
+    assert tim["replica_steps"] == (s + 1) * R * prob["n_steps"]
+    plain = dict(prob, free_ensemble=False)
+    res0, _ = ppp.run(plain)
+    for key in ("dF_je", "dF_fluct", "dF_je_se", "xi_mean"):
+        assert np.array_equal(res0[key], res[key], equal_nan=True), key
+    assert np.array_equal(res0["xi_hist"], res["xi_hist"])
 
 
 SEQ_CASES = [

@@ -538,3 +538,93 @@ def test_literal_work_binning_hand_case():
     # with the bin centre (x = 1.75) as representative: f = 2.37, -2.98, so w3 = trunc(2 - 2.98) = 0
     fc = [0.5 * k * ((1.75 - b) ** 2 - (1.75 - a) ** 2) / dWb for a, b in ((l1, l2), (l2, l3))]
     assert int(np.trunc(np.trunc(fc[0]) + fc[1])) == 0
+
+
+# ---------------------------------------------------------------------------
+# Turn-on free energy (Sec. II, Eqs. 5-7, 10, 15; App. A)
+
+def test_turn_on_quadrature_matches_harmonic_closed_form():
+    """dF(lambda, k) = F(lambda, k) - F_0 by quadrature against the ratio of two
+    Gaussian integrals, and the two sides of Eq. 7 against their Gaussian
+    moments: <(x - lambda)^2> = kT/(kappa + k) + (kappa lambda/(kappa + k))^2
+    restrained, kT/kappa + lambda^2 free."""
+    kappa, k, kT = 4.0, 2.0, 1.0
+    lam = np.array([-1.0, -0.3, 0.0, 0.4, 1.2])
+    dF, lower, upper = quadrature.turn_on_1d(lambda x: 0.5 * kappa * x * x, lam, k, kT)
+    assert np.allclose(dF, quadrature.harmonic_turn_on_closed_form(kappa, k, kT, lam), rtol=0, atol=1e-10)
+    assert np.allclose(lower, 0.5 * k * (kT / (kappa + k) + (kappa * lam / (kappa + k)) ** 2), atol=1e-10)
+    assert np.allclose(upper, 0.5 * k * (kT / kappa + lam ** 2), atol=1e-10)
+    # Eq. 7 holds strictly for the exact values (Jensen), here and for the double well
+    assert np.all(lower < dF) and np.all(dF < upper)
+    dF2, lo2, up2 = quadrature.turn_on_1d(quadrature.double_well(), np.linspace(-1.5, 1.5, 7), 20.0, kT)
+    assert np.all(lo2 < dF2) and np.all(dF2 < up2)
+
+
+def _free_run(prob):
+    prob = dict(prob, free_ensemble=True, w_half_bins=0)
+    xi, kept, _ = oracle.run(prob)
+    return prob, estimators.estimate(prob, xi, kept, with_appc=False)
+
+
+def test_turn_on_estimators_harmonic_closed_form():
+    """Eq. 5 (restrained samples) and Eq. 6 (free samples) at lambda_1 and lambda_s
+    against the closed form, G of Eq. 15 against F(lambda_j) - F(lambda_1) -
+    dF(lambda_1), and Eq. 10's average against 1.  kappa > k keeps the variance
+    of Eq. 5's average finite; the lambda range is not symmetric, so lambda_1 and
+    lambda_s cannot be confused."""
+    kappa, k, kT = 4.0, 2.0, 1.0
+    base = ppp_inputs.config_harmonic_1d(kappa=kappa, k=k, n_replicas=96, n_steps=20000)
+    base["lambda"] = list(np.linspace(-1.0, 0.4, 8))
+    base["n_blocks"] = 16
+    prob, r = _free_run(base)
+    on = r["turn_on"]
+    lam = np.asarray(prob["lambda"])
+    ex = quadrature.harmonic_turn_on_closed_form(kappa, k, kT, lam)
+    for key, want in (("eq5_first", ex[0]), ("eq6_first", ex[0]), ("eq5_last", ex[-1]), ("eq6_last", ex[-1])):
+        assert abs(on[key] - want) < 4.0 * on[key + "_se"], (key, on[key], want, on[key + "_se"])
+        assert on[key + "_se"] < 0.05
+    assert abs(on["eq10_log"]) < 4.0 * on["eq10_log_se"]
+    F, _, _ = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    G_exact = (F - F[0]) - ex[0]
+    assert np.all(np.abs(r["G"] - G_exact) < 4.0 * r["G_se"] + 1e-12)
+    assert on["free_n"] == prob["n_replicas"] * oracle.samples_per_replica(prob)
+    assert abs(on["free_mean"]) < 0.05 and abs(on["free_std"] - np.sqrt(kT / kappa)) < 0.02
+
+
+def test_turn_on_estimators_obey_eq7_on_any_sample():
+    """Jensen holds for sample averages too: kT ln mean(exp(beta u)) >= mean(u) and
+    -kT ln mean(exp(-beta u)) <= mean(u), so Eq. 5's estimate is never below the
+    lower bound and Eq. 6's never above the upper one, whatever the sample."""
+    rng = np.random.default_rng(4)
+    lam, k, kT = np.array([0.3, 0.9, 1.7]), 7.0, 0.6
+    for _ in range(20):
+        x1, xs, x0 = rng.normal(0.2, 0.5, 50), rng.normal(1.5, 0.3, 40), rng.normal(0.0, 1.0, 60)
+        v = estimators.turn_on_values(x1, xs, x0, lam, k, kT, 0.0)
+        assert v["eq5_first"] >= 0.5 * k * np.mean((x1 - lam[0]) ** 2)
+        assert v["eq5_last"] >= 0.5 * k * np.mean((xs - lam[-1]) ** 2)
+        assert v["eq6_first"] <= 0.5 * k * np.mean((x0 - lam[0]) ** 2)
+        assert v["eq6_last"] <= 0.5 * k * np.mean((x0 - lam[-1]) ** 2)
+    # one sample each: the averages are single terms, so Eqs. 5 and 6 equal the bounds
+    v = estimators.turn_on_values(np.array([0.5]), np.array([2.0]), np.array([-0.1]), lam, k, kT, 0.0)
+    assert np.isclose(v["eq5_first"], 0.5 * k * 0.2 ** 2) and np.isclose(v["eq6_last"], 0.5 * k * 1.8 ** 2)
+
+
+def test_turn_on_estimators_double_well_quadrature():
+    """A shallow double well, U = (x^2 - 1)^2 (barrier 1 kT), with k = 2: both
+    estimates at both ends against quadrature, the bounds of Eq. 7 bracketing
+    them, Eq. 10's average near 1.  Eq. 5's integrand is the unrestrained
+    density itself, so it converges only when the restrained window visits the
+    whole of it: here the restraint is soft and the barrier low, and the well
+    curvature 8 exceeds k, which keeps the variance of that average finite."""
+    base = ppp_inputs.config_1d(n_replicas=96, n_steps=20000, n_windows=11, seed=7)
+    base.update({"k": 2.0, "pot_a": 1.0, "n_blocks": 16})
+    base["lambda"] = list(np.linspace(-1.2, 0.9, 11))
+    prob, r = _free_run(base)
+    on = r["turn_on"]
+    lam = np.asarray(prob["lambda"])
+    dF, lower, upper = quadrature.turn_on_1d(quadrature.double_well(a=1.0), lam[[0, -1]], 2.0, 1.0)
+    for key, want in (("eq5_first", dF[0]), ("eq6_first", dF[0]), ("eq5_last", dF[1]), ("eq6_last", dF[1])):
+        assert abs(on[key] - want) < 4.0 * on[key + "_se"] + 0.01, (key, on[key], want, on[key + "_se"])
+    assert abs(on["lower_first"] - lower[0]) < 0.05 and abs(on["upper_first"] - upper[0]) < 0.2
+    assert on["lower_first"] < on["eq5_first"] and on["eq6_first"] < on["upper_first"]
+    assert abs(on["eq10_log"]) < 4.0 * on["eq10_log_se"] + 0.01
