@@ -29,8 +29,8 @@ FP64_PEAK = 78.6e12
 # 1024: FETCH_SIZE reads 524308 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  A record
 # holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain10": {"sources_sha1": "46bbfd2293500c5288d24c90c1b7bc42f5dd1f76", "kernel": "sim_chain<float,5,2>",
-                "fetch_kib": 179.0, "fetch_scale": 2.0, "write_kib": 10146.125, "write_scale": 1.0},
+    "chain10": {"sources_sha1": "9e2866dd52c828336e0c35b153becfbd88854732", "kernel": "sim_chain<float,5,2>",
+                "fetch_kib": 214.0, "fetch_scale": 2.0, "write_kib": 10146.125, "write_scale": 1.0},
 }
 KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
                   "ppp_launch.hpp")
@@ -245,6 +245,35 @@ def sweep_study(args):
                                "one batched graph", "replica_steps": rs, "seconds": el, "rows": rows}), flush=True)
 
 
+def turn_on_study(args):
+    """Turn-on free energy (Sec. II, Eqs. 5-7, 10, 15) with the unrestrained ensemble
+    run beside the windows: the 10-bead chain workload (fp32 forces), and the 1-D
+    double well in two settings, the bench one (U = 5 (x^2 - 1)^2, k = 50, windows
+    in [-1.5, 1.5]), where the restrained window never visits the far well, and a
+    shallow one (U = (x^2 - 1)^2, k = 2), where it does."""
+    import numpy as np
+    import torch
+    import paper_1105_4840_amd as ppp
+    import ppp_inputs
+    rows = []
+    p = ppp_inputs.config_chain10(n_replicas=1024, n_steps=40000, seed=21)
+    p["free_ensemble"] = True
+    t0 = time.perf_counter()
+    r, tim = ppp.run(p)
+    torch.cuda.synchronize()
+    rows.append({"case": "chain10 fp32", "seconds": time.perf_counter() - t0, "replica_steps": tim["replica_steps"],
+                 "turn_on": r["turn_on"], "dF_je_end": float(r["dF_je"][-1]), "G_end": float(r["G"][-1]),
+                 "G_se_end": float(r["G_se"][-1])})
+    for name, a, k, lam in (("1d double well a=5 k=50", 5.0, 50.0, (-1.5, 1.5)),
+                            ("1d double well a=1 k=2", 1.0, 2.0, (-1.2, 0.9))):
+        q = ppp_inputs.config_1d(n_replicas=1024, n_steps=40000, n_windows=21, seed=22)
+        q.update({"pot_a": a, "k": k, "free_ensemble": True, "lambda": list(np.linspace(lam[0], lam[1], 21))})
+        r, tim = ppp.run(q)
+        rows.append({"case": name, "replica_steps": tim["replica_steps"], "turn_on": r["turn_on"],
+                     "dF_je_end": float(r["dF_je"][-1])})
+    print(json.dumps({"study": "turn-on free energy", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +287,7 @@ def main():
                     help="dF error at equal budget, uniform vs learned windows (32-bead chain)")
     ap.add_argument("--ref-steps", type=int, default=40000)
     ap.add_argument("--sweep", action="store_true", help="tau and k sweep of the 10-bead chain in one batched graph")
+    ap.add_argument("--turn-on", action="store_true", help="turn-on free energy study (unrestrained ensemble)")
     ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
     ap.add_argument("--sequential", action="store_true",
                     help="run the workload with the sequential pulling protocol (each replica runs the "
@@ -287,6 +317,10 @@ def main():
     if args.sweep:
         torch.cuda.set_device(0)
         sweep_study(args)
+        return
+    if args.turn_on:
+        torch.cuda.set_device(0)
+        turn_on_study(args)
         return
     fn, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
