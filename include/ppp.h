@@ -196,6 +196,18 @@ typedef struct {
     double *turn_on;                   /* [PPP_ON_NFIELDS] */
     double *G, *G_se;                  /* [s] Eq. 15 */
     uint64_t *xi_hist_free;            /* [K] histogram of x_0 */
+    /* [s] the reverse path lambda_j -> lambda_1 by App. C from rho_2 .. rho_j with
+     * the work of moving the centre back, dW^rev_i(x) = k/2 [(x - lambda_i)^2 -
+     * (x - lambda_{i+1})^2] (x at the bin centre, floor to bins), checked against the
+     * forward distribution (Crooks fluctuation theorem; Kofke's overlap, Sec. V):
+     * a forward bin w, work in [w, w + j-1) dW after j-1 steps, meets reverse bin
+     * -w - (j-1).  NaN without App. C (M = 0). */
+    double *dF_rev_hist;               /* +kT ln sum_v Omega^rev_j(v) exp(-beta v dW) */
+    double *crooks_ovl;                /* sum_w min(Omega_j(w), Omega^rev_j(-w - (j-1))) */
+    double *dF_crooks;                 /* over the bins both hold, weighted by that minimum:
+                                          W_w - kT ln(Omega_j(w) / Omega^rev_j(-w - (j-1))),
+                                          W_w = (w + (j-1)/2) dW */
+    double *work_hist_rev;             /* [s*(2M+1)], Omega^rev_j, bin v at index v + M */
 } ppp_result;
 
 typedef struct {

@@ -20,6 +20,10 @@ Readings taken here (each also listed with its reason in the design notes):
   distribution too; Omega_1 is the point mass at W = 0 (no step taken);
 * work outside [-M dW, (M+1) dW) is dropped and reported as lost mass.
 
+The reverse path (lambda_j back to lambda_1) is built the same way from the
+windows the reverse steps start from, and checked against the forward one
+with Crooks' fluctuation theorem and the overlap of the two (Sec. V).
+
 From Omega_j: dF^JE by Eq. 12 / App. B.5 (normalised average of
 exp(-beta W)), with W taken at the left bin edge w dW (each of the j-1 floors
 rounds down, so the true work lies in [w dW, (w + j - 1) dW)), and with the
@@ -130,6 +134,63 @@ def work_distributions_literal(prob, hist, n):
         if tot > 0:
             je[j] = -kT * np.log(np.sum(omega[j] * np.exp(-beta * wv * dWb)) / tot)
     return {"work_hist_literal": omega, "dF_je_hist_literal": je}
+
+
+def work_distributions_reverse(prob, hist, n, omega_fwd):
+    """The reverse path lambda_j -> lambda_1 (Sec. V: forward and reverse work
+    distributions; Crooks fluctuation theorem; Kofke's overlap).  Omega^rev_j is
+    built like Omega_j, each step i+1 -> i from the x distribution of the window
+    it starts from, rho_{i+1}, with the work of moving the centre back,
+    dW^rev_i(x) = k/2 [(x - lambda_i)^2 - (x - lambda_{i+1})^2] at the bin centre,
+    floor to bins.  After j folds (0-based j) a work bin w holds work in
+    [w, w + j) dW in either direction, so the forward bin w and the reverse
+    bin -w - j cover opposite intervals.  From them:
+      dF_rev_hist_j = +kT ln sum_v Omega^rev_j(v) exp(-beta v dW) / sum Omega^rev_j
+        (reverse JE: <exp(-beta W_rev)> = exp(+beta dF_j));
+      crooks_ovl_j = sum_w min(Omega_j(w), Omega^rev_j(-w - j));
+      dF_crooks_j: Crooks' P_f(W) / P_r(-W) = exp(beta (W - dF)) read in every bin
+        both distributions hold, dF = W - kT ln(P_f / P_r) with W at the middle
+        (w + j/2) dW of the common interval, averaged with weights
+        min(P_f, P_r)."""
+    lam = np.asarray(prob["lambda"], dtype=np.float64)
+    s = len(lam)
+    k = float(prob["k"]); kT = float(prob["kT"]); beta = 1.0 / kT
+    M = int(prob["w_half_bins"]); dWb = float(prob["w_bin"])
+    K = int(prob["xi_nbins"]); x0 = float(prob["xi_min"]); dx = float(prob["xi_bin"])
+    nb = 2 * M + 1
+    xb = x0 + (np.arange(K) + 0.5) * dx
+    omega = np.zeros((s, nb))
+    omega[0, M] = 1.0
+    for j in range(1, s):
+        rho = hist[j] / max(int(n[j]), 1)                 # the step lambda_j -> lambda_{j-1}
+        dW = 0.5 * k * ((xb - lam[j - 1]) ** 2 - (xb - lam[j]) ** 2)
+        shifts = np.floor(dW / dWb).astype(np.int64)
+        prev = omega[j - 1]
+        cur = omega[j]
+        for b in np.nonzero(rho)[0]:
+            sb = int(shifts[b])
+            lo = max(0, -sb); hi = min(nb, nb - sb)
+            if lo < hi:
+                cur[lo + sb:hi + sb] += rho[b] * prev[lo:hi]
+    wv = np.arange(-M, M + 1, dtype=np.float64)
+    rev = np.full(s, np.nan); ovl = np.full(s, np.nan); crooks = np.full(s, np.nan)
+    for j in range(s):
+        tot = omega[j].sum()
+        if tot > 0:
+            rev[j] = kT * np.log(np.sum(omega[j] * np.exp(-beta * wv * dWb)) / tot)
+        pf = omega_fwd[j]
+        pr = np.zeros(nb)                                 # pr[w + M] = Omega^rev_j(-w - j)
+        for w in range(-M, M + 1):
+            v = -w - j
+            if -M <= v <= M:
+                pr[w + M] = omega[j][v + M]
+        m = np.minimum(pf, pr)
+        ovl[j] = m.sum()
+        both = (pf > 0) & (pr > 0)
+        if np.any(both):
+            W = (wv[both] + 0.5 * j) * dWb
+            crooks[j] = np.sum(m[both] * (W - kT * np.log(pf[both] / pr[both]))) / np.sum(m[both])
+    return {"work_hist_rev": omega, "dF_rev_hist": rev, "crooks_ovl": ovl, "dF_crooks": crooks}
 
 
 def product_form(prob, hist, n):

@@ -260,6 +260,7 @@ def estimate(prob, xi, kept, with_appc=True):
     if with_appc and int(prob.get("w_half_bins", 0)) > 0:
         res.update(appc.work_distributions(prob, hist, n))
         res.update(appc.work_distributions_literal(prob, hist, n))
+        res.update(appc.work_distributions_reverse(prob, hist, n, res["work_hist"]))
     if prob.get("free_ensemble", False):
         on, res["G"], res["G_se"] = turn_on(prob, xi, kept, res["dF_je"])
         res["turn_on"] = on

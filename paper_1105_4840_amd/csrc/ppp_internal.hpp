@@ -36,8 +36,13 @@ enum OutField : int {
     O_KISH, O_OVL, O_DL_SIGMA, O_DL_REACH, O_CRIT,
     O_DF_FLUCT_LIT, O_DF_GAUSS_LIT, O_DF_JE_HIST_LIT,
     O_G, O_G_SE,            // Eq. 15, with the free ensemble only
+    O_DF_REV_HIST, O_CROOKS_OVL, O_DF_CROOKS,   // reverse-path work distribution checks
     O_NFIELDS
 };
+
+// App. C work-distribution chains: 0 the primary reading, 1 the listing as
+// printed, 2 the reverse path (lambda_j back to lambda_1).
+constexpr int kAppcChains = 3;
 
 // Jackknife leave-one-out profiles stored per block: JE, fluct, gauss, com, G.
 constexpr int JK_FIELDS = 5;
@@ -83,12 +88,12 @@ struct DevProblem {
     int64_t off_jack_turn;  // double [B][JK_TURN]
     int64_t off_out;        // double [O_NFIELDS][s]
     int64_t off_turn;       // double [PPP_ON_NFIELDS]
-    // App. C in two chains: 0 the primary reading, 1 the paper's listing as printed
-    int64_t off_pairs_shift;// int32 [2][s][K] (chain 1: floor of the work in bins)
+    // App. C, kAppcChains chains
+    int64_t off_pairs_shift;// int32 [3][s][K] (chain 1: floor of the work in bins)
     int64_t off_pairs_ceil; // int32 [s][K] (chain 1: its ceiling)
-    int64_t off_pairs_prob; // double [2][s][K]
-    int64_t off_npairs;     // int32 [2][s]
-    int64_t off_omega;      // double [2][s][2M+1]
+    int64_t off_pairs_prob; // double [3][s][K]
+    int64_t off_npairs;     // int32 [3][s]
+    int64_t off_omega;      // double [3][s][2M+1]
 };
 
 // n_reps consecutive replicas of one problem, starting at replica rep_begin of

@@ -33,7 +33,7 @@ __global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ 
         double *om = dptr(ws, P.off_omega);
         const int64_t nb = 2 * (int64_t)P.w_half_bins + 1;
         const int64_t no = (int64_t)P.n_windows * nb;
-        for (int64_t i = tid; i < 2 * no; i += stride)     // both chains; Omega_1: W = 0
+        for (int64_t i = tid; i < kAppcChains * no; i += stride)     // every chain; Omega_1: W = 0
             om[i] = (i % no == P.w_half_bins) ? 1.0 : 0.0;
     }
     if (blockIdx.y == 0 && tid < n_tickets) tickets[tid] = 0;
@@ -42,7 +42,7 @@ __global__ void k_init(const DevProblem *__restrict__ probs, char *__restrict__ 
 hipError_t launch_init(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_k, int max_m,
                        int *d_tickets, int n_tickets, hipStream_t stream) {
     int64_t work = (int64_t)max_windows * max_k;
-    const int64_t wo = 2 * (int64_t)max_windows * (2 * (int64_t)max_m + 1);
+    const int64_t wo = kAppcChains * (int64_t)max_windows * (2 * (int64_t)max_m + 1);
     if (wo > work) work = wo;
     int nb = (int)((work + 255) / 256);
     if (nb < 1) nb = 1;
@@ -347,7 +347,9 @@ hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, h
 // floor(dW_i(x) / dW).  Chain 1, the listing as printed: x at the bin's upper
 // edge and truncation toward zero of W = w dW + dW_i(x), i.e. the move is
 // floor(f) for w + f >= 0 and ceil(f) below, f = dW_i(x) / dW; its pairs keep
-// both and merge only where both agree.
+// both and merge only where both agree.  Chain 2, the reverse path: the bins of
+// rho_{i+1} with the work of moving the centre back, dW^rev_i(x) = k/2
+// [(x - lambda_i)^2 - (x - lambda_{i+1})^2], x at the bin centre, move floor.
 //
 // One 256-thread block per (window step, problem, chain).  The bins are taken 256
 // at a time: the non-empty ones are compacted in order, run heads are marked, and
@@ -383,11 +385,12 @@ __global__ __launch_bounds__(256) void k_appc_pairs(const DevProblem *__restrict
     const int64_t sK = (int64_t)P.n_windows * K;
     const double *lam = dptr(ws, P.off_lambda);
     const double *tot = dptr(ws, P.off_tot);
-    const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)i * K;
+    const int src = chain == 2 ? i + 1 : i;         // window whose x distribution is folded in
+    const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)src * K;
     int *key0 = reinterpret_cast<int *>(ws + P.off_pairs_shift) + chain * sK + (int64_t)i * K;
     int *key1 = reinterpret_cast<int *>(ws + P.off_pairs_ceil) + (int64_t)i * K;   // chain 1 only
     double *prob = dptr(ws, P.off_pairs_prob) + chain * sK + (int64_t)i * K;
-    const double n = tot[(int64_t)i * A_NFIELDS + A_N];
+    const double n = tot[(int64_t)src * A_NFIELDS + A_N];
     const double li = lam[i], lj = lam[i + 1];
     __shared__ int s_scan[256];
     __shared__ int s_k0[256], s_k1[256], s_head[256];
@@ -400,9 +403,10 @@ __global__ __launch_bounds__(256) void k_appc_pairs(const DevProblem *__restrict
         double pb = 0.0;
         if (c != 0ull) {
             pb = (double)c / n;
-            if (chain == 0) {
+            if (chain != 1) {
                 const double xb = P.xi_min + ((double)b + 0.5) * P.xi_bin;
-                const double dW = 0.5 * P.k * ((xb - lj) * (xb - lj) - (xb - li) * (xb - li));
+                const double la = chain == 0 ? li : lj, lb = chain == 0 ? lj : li;   // from la to lb
+                const double dW = 0.5 * P.k * ((xb - lb) * (xb - lb) - (xb - la) * (xb - la));
                 k0 = k1 = clamp_shift(floor(dW / P.w_bin));
             } else {
                 const double xb = P.xi_min + ((double)b + 1.0) * P.xi_bin;
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(256) void k_appc_pairs(const DevProblem *__restrict
             double p = s_pb[t];
             for (int m = t + 1; m < nnz && !s_head[m]; ++m) p += s_pb[m];
             key0[np + rid] = s_k0[t];
-            if (chain) key1[np + rid] = s_k1[t];
+            if (chain == 1) key1[np + rid] = s_k1[t];
             prob[np + rid] = p;
         } else if (t == 0 && nnz > 0) {
             // the chunk opens inside the previous chunk's last run
@@ -442,8 +446,9 @@ __global__ __launch_bounds__(256) void k_appc_pairs(const DevProblem *__restrict
     if (t == 0) reinterpret_cast<int *>(ws + P.off_npairs)[chain * P.n_windows + i] = np;
 }
 
-// Omega_j(w) = sum_t prob_t Omega_{j-1}(w - shift_t), the folding step of App. C.
-// Chain 1 (blockIdx.z) folds as printed: target w > 0 takes source w - floor(f),
+// Omega_j(w) = sum_t prob_t Omega_{j-1}(w - shift_t), the folding step of App. C,
+// for the three chains (blockIdx.z; chain 2, the reverse path, folds like chain 0).
+// Chain 1 folds as printed: target w > 0 takes source w - floor(f),
 // w < 0 takes w - ceil(f); at w = 0 the printed step keeps the mean of the
 // results at w = -1 and w = +1 instead, which are exactly what the targets -1 and
 // +1 compute, so the bin is left unsmoothed here and every reader of Omega_j
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(256) void k_appc_step(const DevProblem *__restrict_
         int64_t first = kNone;
         if (t < cnt) {
             sf = shift[t0 + t];
-            sc = chain ? ceil_s[t0 + t] : sf;
+            sc = chain == 1 ? ceil_s[t0 + t] : sf;
             pt = prob[t0 + t];
             first = w0 - 1 - (int64_t)(sc > sf ? sc : sf);
             if (first + kAppcSpan <= 0 || first >= nb) first = kNone;    // reads nothing in range
@@ -605,7 +610,34 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
     sl = block_sum(sl, sh);
     sm = block_sum(sm, sh);
     vv = block_sum(vv, sh);
-    if (threadIdx.x == 0 && chain == 1) {
+    if (chain == 2) {
+        // reverse JE over the path lambda_j -> lambda_1: <exp(-beta W_rev)> = exp(+beta dF_j)
+        if (threadIdx.x == 0) out[(int64_t)O_DF_REV_HIST * s + j] = tot > 0 ? P.kT * (emax + log(sl / tot)) : NAN;
+        // Crooks and Kofke: the forward distribution against the mirrored reverse one.
+        // After j folds a forward bin w holds work in [w, w + j) dW and a reverse bin v
+        // in [v, v + j) dW, so -W_rev matches forward bin w at v = -w - j.
+        const double *of = dptr(ws, P.off_omega) + (int64_t)j * nb;      // chain 0
+        double ovl = 0, wm = 0, wf = 0;
+        for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+            const int64_t v = 2 * (int64_t)M - b - j;                     // index of bin -w - j
+            if (v < 0 || v >= nb) continue;
+            const double f = of[b], r = om[v];
+            const double m = fmin(f, r);
+            ovl += m;
+            if (f > 0.0 && r > 0.0) {
+                // P_f(W) / P_r(-W) = exp(beta (W - dF)): each common bin gives W - kT ln(P_f / P_r)
+                wm += m;
+                wf += m * (((double)(b - M) + 0.5 * j) * dWb - P.kT * log(f / r));
+            }
+        }
+        ovl = block_sum(ovl, sh);
+        wm = block_sum(wm, sh);
+        wf = block_sum(wf, sh);
+        if (threadIdx.x == 0) {
+            out[(int64_t)O_CROOKS_OVL * s + j] = ovl;
+            out[(int64_t)O_DF_CROOKS * s + j] = wm > 0 ? wf / wm : NAN;
+        }
+    } else if (threadIdx.x == 0 && chain == 1) {
         out[(int64_t)O_DF_JE_HIST_LIT * s + j] = tot > 0 ? -P.kT * (emax + log(sl / tot)) : NAN;
     } else if (threadIdx.x == 0) {
         const double kT = P.kT;
@@ -624,12 +656,12 @@ __global__ __launch_bounds__(256) void k_appc_stats(const DevProblem *__restrict
 hipError_t launch_appc(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_m,
                        hipStream_t stream) {
     if (max_m <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_appc_pairs, dim3(max_windows, n_probs, 2), dim3(256), 0, stream, d_probs, ws);
+    hipLaunchKernelGGL(k_appc_pairs, dim3(max_windows, n_probs, kAppcChains), dim3(256), 0, stream, d_probs, ws);
     const int64_t nb = 2 * (int64_t)max_m + 1;
     const int grid = (int)((nb + 255) / 256);
     for (int j = 1; j < max_windows; ++j)
-        hipLaunchKernelGGL(k_appc_step, dim3(grid, n_probs, 2), dim3(256), 0, stream, d_probs, ws, j);
-    hipLaunchKernelGGL(k_appc_stats, dim3(max_windows, n_probs, 2), dim3(256), 0, stream, d_probs, ws);
+        hipLaunchKernelGGL(k_appc_step, dim3(grid, n_probs, kAppcChains), dim3(256), 0, stream, d_probs, ws, j);
+    hipLaunchKernelGGL(k_appc_stats, dim3(max_windows, n_probs, kAppcChains), dim3(256), 0, stream, d_probs, ws);
     return hipGetLastError();
 }
 

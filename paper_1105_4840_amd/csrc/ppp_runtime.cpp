@@ -314,11 +314,11 @@ int64_t layout_problem(ProblemHost &ph, int64_t at) {
     d.off_out = take((int64_t)O_NFIELDS * s * 8);
     d.off_turn = take(PPP_ON_NFIELDS * 8);
     if (d.w_half_bins > 0) {
-        d.off_pairs_shift = take(2 * s * K * 4);
+        d.off_pairs_shift = take(kAppcChains * s * K * 4);
         d.off_pairs_ceil = take(s * K * 4);
-        d.off_pairs_prob = take(2 * s * K * 8);
-        d.off_npairs = take(2 * s * 4);
-        d.off_omega = take(2 * s * (2 * (int64_t)d.w_half_bins + 1) * 8);
+        d.off_pairs_prob = take(kAppcChains * s * K * 8);
+        d.off_npairs = take(kAppcChains * s * 4);
+        d.off_omega = take(kAppcChains * s * (2 * (int64_t)d.w_half_bins + 1) * 8);
     }
     ph.region_end = at;
     return at;
@@ -473,9 +473,12 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
         put_i64(out->q_bins, o, F(O_Q_BINS), s);
         put(out->work_lost, o, F(O_WORK_LOST), s);
         put(out->dF_je_hist_literal, o, F(O_DF_JE_HIST_LIT), s);
+        put(out->dF_rev_hist, o, F(O_DF_REV_HIST), s);
+        put(out->crooks_ovl, o, F(O_CROOKS_OVL), s);
+        put(out->dF_crooks, o, F(O_DF_CROOKS), s);
     } else {
         for (double *p : {out->dF_je_hist, out->dF_je_hist_mid, out->dF_je_var_paper, out->sigma_w, out->work_lost,
-                          out->dF_je_hist_literal})
+                          out->dF_je_hist_literal, out->dF_rev_hist, out->crooks_ovl, out->dF_crooks})
             if (p) for (int64_t i = 0; i < s; ++i) p[i] = NAN;
         if (out->q_bins) for (int64_t i = 0; i < s; ++i) out->q_bins[i] = 0;
     }
@@ -499,9 +502,10 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
             out->xi_under_over[2 * i] = (uint64_t)std::llround(o[F(O_UNDER) + i]);
             out->xi_under_over[2 * i + 1] = (uint64_t)std::llround(o[F(O_OVER) + i]);
         }
-    if (out->work_hist) {
-        if (appc) HIPCHK(h, hipMemcpy(out->work_hist, h->ws + d.off_omega, s * (2 * (int64_t)d.w_half_bins + 1) * 8, hipMemcpyDeviceToHost));
-    }
+    const int64_t nbw = s * (2 * (int64_t)d.w_half_bins + 1);
+    if (out->work_hist && appc) HIPCHK(h, hipMemcpy(out->work_hist, h->ws + d.off_omega, nbw * 8, hipMemcpyDeviceToHost));
+    if (out->work_hist_rev && appc)
+        HIPCHK(h, hipMemcpy(out->work_hist_rev, h->ws + d.off_omega + 2 * nbw * 8, nbw * 8, hipMemcpyDeviceToHost));
     // the turn-on outputs (Eqs. 5-7, 10, 15)
     std::vector<double> turn(PPP_ON_NFIELDS, NAN);
     if (d.free_ens) HIPCHK(h, hipMemcpy(turn.data(), h->ws + d.off_turn, PPP_ON_NFIELDS * 8, hipMemcpyDeviceToHost));

@@ -156,6 +156,13 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
         assert np.allclose(res["sigma_w"], ref["sigma_w"], rtol=1e-9, atol=1e-12)
         assert np.allclose(res["dF_je_var_paper"], ref["dF_je_var_paper"], rtol=1e-8, atol=1e-14)
         assert np.allclose(res["work_lost"], ref["work_lost"], atol=1e-12)
+        assert np.max(np.abs(res["work_hist_rev"] - ref["work_hist_rev"])) < 1e-12
+        for key in ("dF_rev_hist", "dF_crooks"):
+            assert np.allclose(res[key], ref[key], rtol=1e-9, atol=1e-8, equal_nan=True), key
+        assert np.allclose(res["crooks_ovl"], ref["crooks_ovl"], rtol=0, atol=1e-12)
+    else:
+        for key in ("dF_rev_hist", "crooks_ovl", "dF_crooks"):
+            assert np.all(np.isnan(res[key])), key
     if prob.get("free_ensemble", False):
         on, ron = res["turn_on"], ref["turn_on"]
         for key in ("free_n", "free_blown", "free_under", "free_over"):
@@ -253,6 +260,23 @@ def test_run_without_samples():
     assert np.all(res["xi_hist"] == 0)
     for key in ("dF_je", "dF_fluct", "dF_gauss"):
         assert not np.any(np.isfinite(res[key][1:])) and not np.any(np.isfinite(ref[key][1:])), key
+
+
+def test_paper_scale_work_distributions_fp64():
+    """App. C at the paper's resolution: x bins of 0.001 over [0, 50] (K = 50000,
+    beyond the LDS histogram, so samples go straight to memory) and work bins
+    of 0.01 over +-450 (2M+1 = 90001), both work-distribution chains and the
+    free ensemble's histogram, against the oracle."""
+    _say("case paper-scale App. C")
+    prob = ppp_inputs.config_chain_small(10, n_replicas=70, n_steps=600, n_windows=5, precision="fp64")
+    prob.update({"xi_min": 0.0, "xi_bin": 0.001, "xi_nbins": 50000, "w_bin": 0.01, "w_half_bins": 45000,
+                 "free_ensemble": True})
+    res, tim = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+    _say(f"  appc {tim['appc_ms']:.3f} ms, q_bins {res['q_bins']}")
+    assert res["work_hist"].shape == (5, 90001) and np.all(res["q_bins"][1:] > 100)
 
 
 def _free_case(name):

@@ -628,3 +628,77 @@ def test_turn_on_estimators_double_well_quadrature():
     assert abs(on["lower_first"] - lower[0]) < 0.05 and abs(on["upper_first"] - upper[0]) < 0.2
     assert on["lower_first"] < on["eq5_first"] and on["eq6_first"] < on["upper_first"]
     assert abs(on["eq10_log"]) < 4.0 * on["eq10_log_se"] + 0.01
+
+
+# ---------------------------------------------------------------------------
+# Reverse-path work distributions and the Crooks / Kofke checks (Sec. V)
+
+def test_reverse_work_distribution_brute_force_tiny():
+    """Enumerate every combination of x bins of windows 2 and 3 for the reverse
+    path lambda_3 -> lambda_1: the work bin is floor(dW^rev_2(x_c)/dW) +
+    floor(dW^rev_1(x_b)/dW) with dW^rev_i(x) = k/2 [(x - lambda_i)^2 -
+    (x - lambda_{i+1})^2], its probability rho_2(b) rho_3(c)."""
+    p, hist, n = _tiny_problem()
+    fwd = appc.work_distributions(p, hist, n)
+    out = appc.work_distributions_reverse(p, hist, n, fwd["work_hist"])
+    M = p["w_half_bins"]; dWb = p["w_bin"]
+    lam = p["lambda"]; k = p["k"]
+    xb = p["xi_min"] + (np.arange(5) + 0.5) * p["xi_bin"]
+    ref2 = np.zeros(2 * M + 1); ref3 = np.zeros(2 * M + 1)
+    for b in range(5):
+        wb = int(np.floor(0.5 * k * ((xb[b] - lam[0]) ** 2 - (xb[b] - lam[1]) ** 2) / dWb))
+        ref2[M + wb] += hist[1, b] / n[1]
+        for c in range(5):
+            wc = int(np.floor(0.5 * k * ((xb[c] - lam[1]) ** 2 - (xb[c] - lam[2]) ** 2) / dWb))
+            ref3[M + wb + wc] += hist[1, b] / n[1] * hist[2, c] / n[2]
+    assert np.allclose(out["work_hist_rev"][1], ref2, atol=1e-15)
+    assert np.allclose(out["work_hist_rev"][2], ref3, atol=1e-15)
+    assert out["dF_rev_hist"][0] == 0.0 and out["crooks_ovl"][0] == 1.0 and out["dF_crooks"][0] == 0.0
+
+
+def _gaussian_windows(kappa, k, kT, lam, dx, lo, hi):
+    """Exact restrained densities of kappa/2 x^2 + k/2 (x - lambda)^2, integrated
+    over bins of width dx (as counts out of 10^12), for the windows lam."""
+    from scipy.special import erf
+    edges = np.arange(lo, hi + dx / 2, dx)
+    K = len(edges) - 1
+    F, mu, var = quadrature.harmonic_closed_form(kappa, k, kT, lam)
+    sd = np.sqrt(var)
+    cdf = 0.5 * (1.0 + erf((edges[None, :] - mu[:, None]) / (np.sqrt(2.0) * sd[:, None])))
+    n = 10 ** 12
+    hist = np.diff(cdf, axis=1) * n
+    return hist, np.full(len(lam), n, dtype=np.int64), F - F[0], K
+
+
+def test_crooks_relation_on_exact_gaussian_windows():
+    """With the exact restrained densities of a harmonic well in place of sampled
+    histograms, every step's work is linear in x, the forward and reverse path
+    work distributions are Gaussian, and Crooks' P_f(W) / P_r(-W) =
+    exp(beta (W - dF)) holds exactly in the continuum: binned finely, the log
+    ratio over the bins both distributions hold has slope beta in W and
+    intercept -beta dF (the closed form), the reverse exponential average gives
+    dF, and the overlap-weighted Crooks estimate gives dF."""
+    kappa, k, kT = 4.0, 20.0, 0.7
+    lam = np.linspace(-1.0, 0.6, 5)
+    hist, n, dF, K = _gaussian_windows(kappa, k, kT, lam, 0.0005, -3.0, 3.0)
+    M = 600; dWb = 0.02      # coarse work bins: a mirror off by j bins would move dF by j dW
+    p = {"lambda": lam, "k": k, "kT": kT, "w_half_bins": M, "w_bin": dWb,
+         "xi_nbins": K, "xi_min": -3.0, "xi_bin": 0.0005}
+    fwd = appc.work_distributions(p, hist, n)
+    rev = appc.work_distributions_reverse(p, hist, n, fwd["work_hist"])
+    for j in range(1, len(lam)):
+        pf = fwd["work_hist"][j]
+        w = np.arange(-M, M + 1)
+        v = -w - j
+        ok = (v >= -M) & (v <= M)
+        pr = np.zeros_like(pf); pr[ok] = rev["work_hist_rev"][j][v[ok] + M]
+        both = (pf > 1e-6) & (pr > 1e-6)
+        W = (w[both] + 0.5 * j) * dWb
+        slope, icpt = np.polyfit(W, np.log(pf[both] / pr[both]), 1)
+        assert abs(slope * kT - 1.0) < 0.02, (j, slope * kT)
+        assert abs(-icpt / slope - dF[j]) < 0.02, (j, -icpt / slope, dF[j])
+        assert abs(rev["dF_rev_hist"][j] - dF[j]) < 0.005 + j * dWb   # left-edge W: up to j dW
+        assert abs(rev["dF_crooks"][j] - dF[j]) < 0.005
+        assert 0.0 < rev["crooks_ovl"][j] <= 1.0
+    # the overlap shrinks as the path gets longer
+    assert np.all(np.diff(rev["crooks_ovl"][1:]) < 0)
