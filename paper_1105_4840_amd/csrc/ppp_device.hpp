@@ -23,12 +23,20 @@ __device__ __forceinline__ U4 philox(uint64_t seed, uint32_t c0, uint32_t c1, ui
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        uint32_t n0 = hi1 ^ c1 ^ k0;
-        uint32_t n2 = hi0 ^ c3 ^ k1;
+        // three-input xor in one v_bitop3_b32 (truth table 0x96)
+        uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
         k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
     }
     return U4{c0, c1, c2, c3};
+}
+
+// (r >> 9 + 1/2) 2^-23 in two instructions: the bits 0x3f800000 | (r >> 9)
+// (v_alignbit_b32 of 0x7f and r by 9) are the float 1 + (r >> 9) 2^-23, and
+// subtracting 1 - 2^-24 is exact.
+__device__ __forceinline__ float unit_f32(uint32_t r) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, r, 9u)) - 0.99999994039535522f;
 }
 
 // Four standard normals per Philox block by Box-Muller, in the requested
@@ -54,10 +62,8 @@ template <> struct Normal4<float> {
     __device__ __forceinline__ static void get(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                                                uint32_t c3, float z[4]) {
         U4 r = philox(seed, c0, c1, c2, c3);
-        const float scale = 1.0f / 8388608.0f;      // 2^-23
         const float m2ln2 = -2.0f * 0.69314718055994531f;
-        float ua = ((float)(r.x >> 9) + 0.5f) * scale, ub = ((float)(r.y >> 9) + 0.5f) * scale;
-        float uc = ((float)(r.z >> 9) + 0.5f) * scale, ud = ((float)(r.w >> 9) + 0.5f) * scale;
+        const float ua = unit_f32(r.x), ub = unit_f32(r.y), uc = unit_f32(r.z), ud = unit_f32(r.w);
         float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(ua));
         float rc = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(uc));
         z[0] = ra * __builtin_amdgcn_cosf(ub); z[1] = ra * __builtin_amdgcn_sinf(ub);
