@@ -90,16 +90,26 @@ __device__ __forceinline__ void len_inv(double r2, double &len, double &inv) {
 // ---------------------------------------------------------------------------
 // Running log-sum-exp (m, S): ln sum_k exp(a_k) = m + ln S.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lse_push(double &m, double &S, double a) {
-    if (a > m) { S = S * exp(m - a) + 1.0; m = a; }
-    else { S += exp(a - m); }
-}
 __device__ __forceinline__ void lse_merge(double &m, double &S, double m2, double S2) {
     if (S2 == 0.0) return;
     if (S == 0.0) { m = m2; S = S2; return; }
     double M = fmax(m, m2);
     S = S * exp(m - M) + S2 * exp(m2 - M);
     m = M;
+}
+// Adds a to the running log-sum-exp (m, S) of a, and 2a to (m2, S2), with one
+// exponential: the running maximum of 2a is twice that of a, so its rescaling
+// factor is the square of a's.  t = exp(-|a - m|) serves both branches, so
+// lanes that disagree on a > m still evaluate one exponential.
+__device__ __forceinline__ void lse_push_pair(double &m, double &S, double &m2, double &S2, double a) {
+    const double d = a - m;
+    const bool up = d > 0.0;
+    const double t = exp(up ? -d : d);
+    const double t2 = t * t;
+    S = up ? S * t + 1.0 : S + t;
+    S2 = up ? S2 * t2 + 1.0 : S2 + t2;
+    m = up ? a : m;
+    m2 = 2.0 * m;
 }
 __device__ __forceinline__ double lse_value(double m, double S) {
     return S > 0.0 ? m + log(S) : -INFINITY;

@@ -50,50 +50,74 @@ __device__ __forceinline__ int64_t next_sample_after(const DevProblem &P, int64_
     return P.n_equil + ((after - P.n_equil) / P.sample_every + 1) * P.sample_every;
 }
 
+// Per-replica constants of the sampling step: the forward and reverse exponents
+// a = -beta dW of one sample, evaluated exactly as written below but with the
+// window's lambda values read once per replica instead of once per sample.
+// kind 1: a step to the neighbouring window, a = cf (d - h) with cf = beta k dl,
+// h = dl/2, dl the centre's move, d = xi - lambda_w; kind 2: switching the
+// restraint on or off, a = q e e with e = xi - ref.
+struct SampleCoef {
+    double lam_w;
+    int kind_f, kind_r;
+    double cf, hf, cr, hr;
+    double qf, qr, ref_f, ref_r;
+};
+
+__device__ __forceinline__ SampleCoef sample_coef(const DevProblem &P, const double *lam, int w) {
+    const int s = P.n_windows;
+    SampleCoef c;
+    c.lam_w = lam[w];
+    c.kind_f = c.kind_r = 0;
+    c.cf = c.hf = c.cr = c.hr = c.qf = c.qr = c.ref_f = c.ref_r = 0.0;
+    const double bk = P.beta * P.k;
+    if (w == s) {
+        // the unrestrained ensemble (d = xi - lambda_1): switching the restraint on
+        // at lambda_1 or at lambda_s costs W_H = k/2 (x_0 - lambda)^2 (Eqs. 4, 6)
+        c.kind_f = c.kind_r = 2;
+        c.qf = c.qr = -0.5 * P.beta * P.k;
+        c.ref_f = lam[s];                 // lambda_1
+        c.ref_r = lam[s - 1];
+    } else {
+        if (w + 1 < s) {
+            // a = -beta k/2 [(xi - lambda_{i+1})^2 - (xi - lambda_i)^2] = beta k dl (d - dl/2)
+            const double dl = lam[w + 1] - lam[w];
+            c.kind_f = 1; c.cf = bk * dl; c.hf = 0.5 * dl;
+        } else if (P.free_ens) {
+            // switching the restraint at lambda_s off: a = +beta k/2 d^2 (Eq. 5)
+            c.kind_f = 2; c.qf = 0.5 * P.beta * P.k; c.ref_f = lam[w];
+        }
+        if (w > 0) {
+            const double dl = lam[w - 1] - lam[w];
+            c.kind_r = 1; c.cr = bk * dl; c.hr = 0.5 * dl;
+        } else if (P.free_ens) {
+            c.kind_r = 2; c.qr = 0.5 * P.beta * P.k; c.ref_r = lam[w];   // the same at lambda_1 (Eq. 5)
+        }
+    }
+    return c;
+}
+
 // Folds one sample xi of window w into the replica's accumulator.  The
 // histogram count goes to the workgroup's LDS copy of window w's histogram
 // (lhist) when there is one, else straight to memory.
-__device__ __forceinline__ void accumulate(const DevProblem &P, const double *lam, int w, double xi,
+__device__ __forceinline__ void accumulate(const DevProblem &P, const SampleCoef &C, int w, double xi,
                                            double *acc, unsigned long long *hist, unsigned int *lhist) {
-    const int s = P.n_windows;
-    const double d = xi - lam[w];
+    const double d = xi - C.lam_w;
     acc[A_N] += 1.0;
     acc[A_S1] += d;
     acc[A_S2] += d * d;
     acc[A_XMIN] = fmin(acc[A_XMIN], xi);
     acc[A_XMAX] = fmax(acc[A_XMAX], xi);
-    if (w == s) {
-        // the unrestrained ensemble (d = xi - lambda_1): switching the restraint on
-        // at lambda_1 or at lambda_s costs W_H = k/2 (x_0 - lambda)^2 (Eqs. 4, 6)
-        const double e = xi - lam[s - 1];
-        const double af = -0.5 * P.beta * P.k * d * d, ar = -0.5 * P.beta * P.k * e * e;
-        lse_push(acc[A_MF], acc[A_SF], af);
-        lse_push(acc[A_MF2], acc[A_SF2], 2.0 * af);
-        lse_push(acc[A_MR], acc[A_SR], ar);
-        lse_push(acc[A_MR2], acc[A_SR2], 2.0 * ar);
-    } else {
-        if (w + 1 < s) {
-            // a = -beta k/2 [(xi - lambda_{i+1})^2 - (xi - lambda_i)^2] = beta k dl (d - dl/2)
-            const double dl = lam[w + 1] - lam[w];
-            const double a = P.beta * P.k * dl * (d - 0.5 * dl);
-            lse_push(acc[A_MF], acc[A_SF], a);
-            lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
-        } else if (P.free_ens) {
-            // switching the restraint at lambda_s off: a = +beta k/2 d^2 (Eq. 5)
-            const double a = 0.5 * P.beta * P.k * d * d;
-            lse_push(acc[A_MF], acc[A_SF], a);
-            lse_push(acc[A_MF2], acc[A_SF2], 2.0 * a);
-        }
-        if (w > 0) {
-            const double dl = lam[w - 1] - lam[w];
-            const double a = P.beta * P.k * dl * (d - 0.5 * dl);
-            lse_push(acc[A_MR], acc[A_SR], a);
-            lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
-        } else if (P.free_ens) {
-            const double a = 0.5 * P.beta * P.k * d * d;   // the same at lambda_1 (Eq. 5)
-            lse_push(acc[A_MR], acc[A_SR], a);
-            lse_push(acc[A_MR2], acc[A_SR2], 2.0 * a);
-        }
+    if (C.kind_f == 1) {
+        lse_push_pair(acc[A_MF], acc[A_SF], acc[A_MF2], acc[A_SF2], C.cf * (d - C.hf));
+    } else if (C.kind_f == 2) {
+        const double e = xi - C.ref_f;
+        lse_push_pair(acc[A_MF], acc[A_SF], acc[A_MF2], acc[A_SF2], C.qf * e * e);
+    }
+    if (C.kind_r == 1) {
+        lse_push_pair(acc[A_MR], acc[A_SR], acc[A_MR2], acc[A_SR2], C.cr * (d - C.hr));
+    } else if (C.kind_r == 2) {
+        const double e = xi - C.ref_r;
+        lse_push_pair(acc[A_MR], acc[A_SR], acc[A_MR2], acc[A_SR2], C.qr * e * e);
     }
     const double fb = floor((xi - P.xi_min) / P.xi_bin);
     if (fb < 0.0) acc[A_UNDER] += 1.0;
@@ -162,6 +186,7 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(ws + P.off_hist);
     T *st = state_ptr<T>(ws, P) + gs * 2;
     const double lam_w = lam[w];
+    const SampleCoef coef = sample_coef(P, lam, w);
     const double x_start = reinterpret_cast<const double *>(ws + P.off_init)[0];
     const int64_t n_end = step_end < s0 + P.n_steps ? step_end : s0 + P.n_steps;
 
@@ -206,7 +231,7 @@ __device__ __forceinline__ void sim_1d_replica(const DevProblem &P, const WorkIt
             n_sample += P.sample_every;
             const double xi = (double)x;
             if (!isfinite(xi) || fabs(xi) > P.xi_bound) { acc[A_BLOWN] = 1.0; alive = false; break; }
-            accumulate(P, lam, w, xi, acc, hist, lhist);
+            accumulate(P, coef, w, xi, acc, hist, lhist);
         }
     }
     for (int f = 0; f < A_NFIELDS; ++f) acc_g[f] = acc[f];
@@ -483,6 +508,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     double *acc_g = reinterpret_cast<double *>(ws + P.off_acc) + grec * A_NFIELDS;
     T *st = state_ptr<T>(ws, P) + gi * 6 * NPAD;
     const double lam_w = lam[w];
+    const SampleCoef coef = sample_coef(P, lam, w);
     const int64_t n_end = step_end < s0 + P.n_steps ? step_end : s0 + P.n_steps;
     auto centre = [&](int64_t n) { return stage == 0 ? centre_at(P, lam_w, n) : lam_w; };
     const T kr = (T)window_k(P, w);
@@ -591,7 +617,7 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
                 if (g == owner) acc[A_BLOWN] = 1.0;
                 alive = false;
             } else if (g == owner) {
-                accumulate(P, lam, w, xi, acc, hist, lhist_w);
+                accumulate(P, coef, w, xi, acc, hist, lhist_w);
             }
         }
     }
