@@ -245,33 +245,39 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
             for (int j = 0; j < s; ++j) OUT(O_G, j) = NAN;
         }
     }
-    // (d) jackknife: block b removed from every window
+    // (d) jackknife: block b removed from every window.  First every (block,
+    // step) term from its window without that block, in parallel; then the
+    // prefix sums per block.  Blocks are merged in block order as before.
+    auto loo = [&](int b, int w, double *a) {
+        acc_empty(a);
+        for (int c = 0; c < B; ++c)
+            if (c != b) acc_merge(a, blk + ((int64_t)w * B + c) * A_NFIELDS);
+    };
     if (B > 1) {
+        for (int q = t; q < B * (s - 1); q += blockDim.x) {
+            const int b = q / (s - 1), j = q % (s - 1) + 1;
+            double a[A_NFIELDS];
+            loo(b, j - 1, a);
+            const WinStat st = win_stat(a, lam[j - 1]);
+            double dje, dfl, dga;
+            step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
+            double *jb = jack + (int64_t)b * JK_FIELDS * s;
+            jb[0 * s + j] = dje; jb[1 * s + j] = dfl; jb[2 * s + j] = dga;
+        }
+        __syncthreads();
         for (int b = t; b < B; b += blockDim.x) {
             double je = 0, fl = 0, ga = 0;
             double *jb = jack + (int64_t)b * JK_FIELDS * s;
             jb[0 * s] = 0; jb[1 * s] = 0; jb[2 * s] = 0; jb[3 * s] = 0;
-            // window w without block b
-            auto loo = [&](int w, double *a) {
-                acc_empty(a);
-                for (int c = 0; c < B; ++c)
-                    if (c != b) acc_merge(a, blk + ((int64_t)w * B + c) * A_NFIELDS);
-            };
-            double a1[A_NFIELDS];
             for (int j = 1; j < s; ++j) {
-                double a[A_NFIELDS];
-                loo(j - 1, a);
-                if (j == 1) for (int f = 0; f < A_NFIELDS; ++f) a1[f] = a[f];
-                const WinStat st = win_stat(a, lam[j - 1]);
-                double dje, dfl, dga;
-                step_terms(P, st, lam[j - 1], lam[j], dje, dfl, dga);
-                je += dje; fl += dfl; ga += dga;
+                je += jb[0 * s + j]; fl += jb[1 * s + j]; ga += jb[2 * s + j];
                 jb[0 * s + j] = je; jb[1 * s + j] = fl; jb[2 * s + j] = ga; jb[3 * s + j] = 0.5 * (je + fl);
             }
             if (P.free_ens) {
-                double as[A_NFIELDS], a0[A_NFIELDS];
-                loo(s - 1, as);
-                loo(s, a0);
+                double a1[A_NFIELDS], as[A_NFIELDS], a0[A_NFIELDS];
+                loo(b, 0, a1);
+                loo(b, s - 1, as);
+                loo(b, s, a0);
                 const TurnOn on = turn_on(P, a1, as, a0, je);
                 double *jt = dptr(ws, P.off_jack_turn) + (int64_t)b * JK_TURN;
                 jt[0] = on.eq5_first; jt[1] = on.eq6_first; jt[2] = on.eq5_last; jt[3] = on.eq6_last; jt[4] = on.eq10;
@@ -321,16 +327,20 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
             OUT(fields[q], j) = se;
         }
     }
-    // (e) overlap of adjacent histograms: sum_b min(rho_i(b), rho_{i+1}(b))
-    for (int i = 0; i + 1 < s; ++i) {
-        const double ni = tot[(int64_t)i * A_NFIELDS + A_N], nj = tot[(int64_t)(i + 1) * A_NFIELDS + A_N];
-        double part = 0;
-        for (int b = t; b < K; b += blockDim.x)
-            part += fmin((double)hist[(int64_t)i * K + b] / ni, (double)hist[(int64_t)(i + 1) * K + b] / nj);
-        const double ovl = block_sum(part, sh);
-        if (t == 0) OUT(O_OVL, i) = ovl;
+    // (e) overlap of adjacent histograms: sum_b min(rho_i(b), rho_{i+1}(b)), one
+    // wavefront per adjacent pair (lanes stride the bins, then a fixed tree)
+    {
+        const int wave = t >> 6, lane = t & 63, n_waves = blockDim.x >> 6;
+        for (int i = wave; i + 1 < s; i += n_waves) {
+            const double ni = tot[(int64_t)i * A_NFIELDS + A_N], nj = tot[(int64_t)(i + 1) * A_NFIELDS + A_N];
+            double part = 0;
+            for (int b = lane; b < K; b += 64)
+                part += fmin((double)hist[(int64_t)i * K + b] / ni, (double)hist[(int64_t)(i + 1) * K + b] / nj);
+            for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off);
+            if (lane == 0) OUT(O_OVL, i) = part;
+        }
+        if (t == 0) OUT(O_OVL, s - 1) = NAN;
     }
-    if (t == 0) OUT(O_OVL, s - 1) = NAN;
 #undef OUT
 }
 
