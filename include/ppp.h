@@ -208,6 +208,13 @@ typedef struct {
                                           W_w - kT ln(Omega_j(w) / Omega^rev_j(-w - (j-1))),
                                           W_w = (w + (j-1)/2) dW */
     double *work_hist_rev;             /* [s*(2M+1)], Omega^rev_j, bin v at index v + M */
+    /* [s] sigma_i as the paper obtains it (Sec. IV A: least-squares fitting of the
+     * x_i distribution): the Gaussian A exp(-(x - mu)^2 / (2 sigma^2)) closest in
+     * least squares to the histogram density count_b / (n xi_bin) at the bin
+     * centres (Levenberg-Marquardt from the sample moments; NaN for windows with
+     * fewer than 3 samples or fewer than 3 non-empty bins); gamma_i^2 = k sigma_i^2 / kT from it; and Eq. 13 with
+     * that gamma_i^2 and the sample means */
+    double *sigma_lsq, *gamma2_lsq, *dF_gauss_lsq;
 } ppp_result;
 
 typedef struct {

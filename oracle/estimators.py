@@ -112,6 +112,58 @@ def profiles(stats, lam, k, kT):
             "dF_fluct_literal": fl_lit, "dF_gauss_literal": g_lit}
 
 
+def gauss_fit(counts, n, x_min, dx, mean, sd):
+    """The paper's sigma (Sec. IV A: sigma_i by least-squares fitting of the x_i
+    distribution): the Gaussian A exp(-(x - mu)^2 / (2 sigma^2)) fitted in least
+    squares to the histogram density counts / (n dx) at the bin centres.  The
+    paper names no algorithm; the one taken here is Levenberg-Marquardt from the
+    sample moments with a fixed schedule, so that a histogram whose least-squares
+    problem has several minima (one that shows only part of the distribution)
+    still gets one defined answer:
+      start A = 1 / (sd sqrt(2 pi)), mu = mean, sigma = sd, damping l = 1e-3;
+      step: solve (J^T J + l diag(J^T J)) d = J^T r for the residual r = y - f;
+      accept if the squared residual does not grow (then l = max(l/10, 1e-15)),
+      else l = 10 l; stop once every component of d is within 1e-14 of its
+      parameter's scale (mu's: |mu| + sigma), when l exceeds 1e12, or after 200
+      steps.  Returns (A, mu, sigma), or NaNs for fewer than 3 samples or fewer
+    than 3 non-empty bins."""
+    counts = np.asarray(counts, dtype=np.float64)
+    if not (n > 2) or not (sd > 0) or np.count_nonzero(counts) < 3:   # three parameters need three points
+        return np.nan, np.nan, np.nan
+    x = x_min + (np.arange(len(counts)) + 0.5) * dx
+    y = counts / (n * dx)
+
+    def cost(A, mu, sg):
+        return float(np.sum((y - A * np.exp(-(x - mu) ** 2 / (2.0 * sg * sg))) ** 2))
+    A, mu, sg = 1.0 / (sd * np.sqrt(2.0 * np.pi)), float(mean), float(sd)
+    lm = 1e-3
+    c0 = cost(A, mu, sg)
+    for _ in range(200):
+        d = x - mu
+        e = np.exp(-d * d / (2.0 * sg * sg))
+        f = A * e
+        r = y - f
+        J = np.stack([e, f * d / sg ** 2, f * d * d / sg ** 3], axis=1)
+        JtJ = J.T @ J
+        Jtr = J.T @ r
+        M = JtJ + lm * np.diag(np.diag(JtJ))
+        with np.errstate(all="ignore"):
+            step = np.linalg.solve(M, Jtr) if np.linalg.det(M) != 0 else np.full(3, np.nan)
+        done = (abs(step[0]) <= 1e-14 * abs(A) and abs(step[1]) <= 1e-14 * (abs(mu) + sg)
+                and abs(step[2]) <= 1e-14 * sg)
+        nA, nm, ns = A + step[0], mu + step[1], abs(sg + step[2])
+        with np.errstate(all="ignore"):
+            c1 = cost(nA, nm, ns)
+        if c1 <= c0:
+            A, mu, sg, c0 = nA, nm, ns, c1
+            lm = max(lm * 0.1, 1e-15)
+        else:
+            lm *= 10.0
+        if done or lm > 1e12:
+            break
+    return A, mu, sg
+
+
 def turn_on_values(x1, xs, x0, lam, k, kT, je_s):
     """Turn-on estimates from the samples of window 1 (x1), window s (xs) and the
     unrestrained ensemble (x0); je_s = dF^JE(lambda_s) of the same samples."""
@@ -256,6 +308,18 @@ def estimate(prob, xi, kept, with_appc=True):
     res["criterion_ok"] = np.abs(dl) <= reach
     rho = hist / np.maximum(n[:, None], 1)
     res["overlap_ovl"] = np.sum(np.minimum(rho[:-1], rho[1:]), axis=1)
+
+    # sigma_i by least-squares fitting (Sec. IV A), gamma_i^2 from it, and Eq. 13 with it
+    sig_lsq = np.array([gauss_fit(hist[w], n[w], float(prob["xi_min"]), float(prob["xi_bin"]), mean[w],
+                                  np.sqrt(var[w]) if n[w] > 1 else np.nan)[2] for w in range(s)])
+    res["sigma_lsq"] = sig_lsq
+    res["gamma2_lsq"] = k * sig_lsq ** 2 / kT
+    g = np.zeros(s)
+    for j in range(1, s):
+        i = j - 1
+        dl = lam[i + 1] - lam[i]
+        g[j] = g[j - 1] + k * dl * (lam[i] - mean[i]) + 0.5 * k * dl * dl * (1.0 - res["gamma2_lsq"][i])
+    res["dF_gauss_lsq"] = g
 
     if with_appc and int(prob.get("w_half_bins", 0)) > 0:
         res.update(appc.work_distributions(prob, hist, n))

@@ -70,6 +70,7 @@ _RESULT_S_I64_2 = ["n_samples", "n_blown_up"]
 _RESULT_P = ["kish_frac", "overlap_ovl", "dlambda_over_sigma", "dlambda_over_reach"]
 _RESULT_LIT = ["dF_fluct_literal", "dF_gauss_literal", "dF_je_hist_literal"]
 _RESULT_REV = ["dF_rev_hist", "crooks_ovl", "dF_crooks"]
+_RESULT_LSQ = ["sigma_lsq", "gamma2_lsq", "dF_gauss_lsq"]
 
 
 class ppp_result(ctypes.Structure):
@@ -78,7 +79,7 @@ class ppp_result(ctypes.Structure):
                 [(n, _dp) for n in _RESULT_P] + [("criterion_ok", _i32p)] + [(n, _dp) for n in _RESULT_LIT] +
                 [("xi_hist", _u64p), ("xi_under_over", _u64p), ("work_hist", _dp)] +
                 [("turn_on", _dp), ("G", _dp), ("G_se", _dp), ("xi_hist_free", _u64p)] +
-                [(n, _dp) for n in _RESULT_REV] + [("work_hist_rev", _dp)])
+                [(n, _dp) for n in _RESULT_REV] + [("work_hist_rev", _dp)] + [(n, _dp) for n in _RESULT_LSQ])
 
 
 class ppp_timings(ctypes.Structure):
@@ -277,7 +278,7 @@ def _result_buffers(prob):
     bufs["criterion_ok"] = np.zeros(s - 1, dtype=np.int32); r.criterion_ok = bufs["criterion_ok"].ctypes.data_as(_i32p)
     bufs["xi_hist"] = np.zeros((s, K), dtype=np.uint64); r.xi_hist = bufs["xi_hist"].ctypes.data_as(_u64p)
     bufs["xi_under_over"] = np.zeros((s, 2), dtype=np.uint64); r.xi_under_over = bufs["xi_under_over"].ctypes.data_as(_u64p)
-    for n in _RESULT_REV:
+    for n in _RESULT_REV + _RESULT_LSQ:
         bufs[n] = np.full(s, np.nan); setattr(r, n, bufs[n].ctypes.data_as(_dp))
     if M > 0:
         bufs["work_hist"] = np.zeros((s, 2 * M + 1)); r.work_hist = bufs["work_hist"].ctypes.data_as(_dp)

@@ -37,6 +37,7 @@ enum OutField : int {
     O_DF_FLUCT_LIT, O_DF_GAUSS_LIT, O_DF_JE_HIST_LIT,
     O_G, O_G_SE,            // Eq. 15, with the free ensemble only
     O_DF_REV_HIST, O_CROOKS_OVL, O_DF_CROOKS,   // reverse-path work distribution checks
+    O_SIGMA_LSQ, O_GAMMA2_LSQ, O_DF_GAUSS_LSQ,   // sigma_i by least-squares Gaussian fit, Eq. 13 with it
     O_NFIELDS
 };
 

@@ -29,7 +29,7 @@ hipError_t launch_init(const DevProblem *d_probs, int n_probs, char *ws, int max
 // replica records -> (window, block) records -> window totals, estimators, diagnostics
 hipError_t launch_reduce(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_blocks,
                          hipStream_t stream);
-hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, hipStream_t stream);
+hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, hipStream_t stream);
 // App. C: shift/probability pairs, the j-th folding step, statistics of Omega
 hipError_t launch_appc(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, int max_m,
                        hipStream_t stream);

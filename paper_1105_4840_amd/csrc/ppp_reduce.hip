@@ -344,8 +344,128 @@ __global__ __launch_bounds__(256) void k_estimators(const DevProblem *__restrict
 #undef OUT
 }
 
-hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, hipStream_t stream) {
+// ---------------------------------------------------------------------------
+// The paper's sigma_i (Sec. IV A: gamma_i^2 = k sigma_i^2 / kT with sigma_i by
+// least-squares fitting of the x_i distribution): the Gaussian A exp(-(x -
+// mu)^2 / (2 sigma^2)) closest in least squares to the histogram density
+// count_b / (n dxi) at the bin centres, by Levenberg-Marquardt from the sample
+// moments.  One workgroup per window; each iteration sums J^T J, J^T r and the
+// squared residual over the bins in one block reduction.
+template <int NV>
+__device__ __forceinline__ void block_sum_vec(double (&v)[NV], double *sh) {
+    for (int q = 0; q < NV; ++q)
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_xor(v[q], off);
+    const int wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < NV; ++q) sh[q * 4 + wave] = v[q];
+    __syncthreads();
+    for (int q = 0; q < NV; ++q) {
+        double t = 0;
+        for (int u = 0; u < n_waves; ++u) t += sh[q * 4 + u];
+        v[q] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gauss_fit(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+    const DevProblem &P = probs[blockIdx.y];
+    const int w = blockIdx.x, s = P.n_windows, K = P.xi_nbins;
+    if (w >= s) return;
+    double *out = dptr(ws, P.off_out);
+    const double *a = dptr(ws, P.off_tot) + (int64_t)w * A_NFIELDS;
+    const unsigned long long *hist = reinterpret_cast<const unsigned long long *>(ws + P.off_hist) + (int64_t)w * K;
+    const double *lam = dptr(ws, P.off_lambda);
+    __shared__ double sh[10 * 4];
+    __shared__ double s_p[3];
+    __shared__ int s_done;
+    const double n = a[A_N];
+    const double m1 = a[A_S1] / n;
+    const double var = (a[A_S2] - n * m1 * m1) / (n - 1.0);
+    double nz[1] = {0.0};                             // non-empty bins
+    for (int b = threadIdx.x; b < K; b += blockDim.x) nz[0] += hist[b] ? 1.0 : 0.0;
+    block_sum_vec<1>(nz, sh);
+    if (!(n > 2.0) || !(var > 0.0) || nz[0] < 3.0) {   // three parameters need three points
+        if (threadIdx.x == 0) { out[(int64_t)O_SIGMA_LSQ * s + w] = NAN; out[(int64_t)O_GAMMA2_LSQ * s + w] = NAN; }
+        return;
+    }
+    const double norm = 1.0 / (n * P.xi_bin);
+    double A = 1.0 / (sqrt(var) * 2.5066282746310002), mu = lam[w] + m1, sg = sqrt(var);
+    double lm = 1e-3;
+    // squared residual of (A, mu, sg)
+    auto cost = [&](double pA, double pm, double ps) {
+        double c[1] = {0.0};
+        const double i2 = 1.0 / (2.0 * ps * ps);
+        for (int b = threadIdx.x; b < K; b += blockDim.x) {
+            const double x = P.xi_min + ((double)b + 0.5) * P.xi_bin, d = x - pm;
+            const double r = (double)hist[b] * norm - pA * exp(-d * d * i2);
+            c[0] += r * r;
+        }
+        block_sum_vec<1>(c, sh);
+        return c[0];
+    };
+    double c0 = cost(A, mu, sg);
+    for (int it = 0; it < 200; ++it) {
+        double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // JtJ (6), Jtr (3), unused
+        const double i2 = 1.0 / (2.0 * sg * sg), is2 = 1.0 / (sg * sg);
+        for (int b = threadIdx.x; b < K; b += blockDim.x) {
+            const double x = P.xi_min + ((double)b + 0.5) * P.xi_bin, d = x - mu;
+            const double e = exp(-d * d * i2);
+            const double f = A * e;
+            const double r = (double)hist[b] * norm - f;
+            const double jA = e, jm = f * d * is2, js = f * d * d * is2 / sg;
+            v[0] += jA * jA; v[1] += jA * jm; v[2] += jA * js;
+            v[3] += jm * jm; v[4] += jm * js; v[5] += js * js;
+            v[6] += jA * r; v[7] += jm * r; v[8] += js * r;
+        }
+        block_sum_vec<10>(v, sh);
+        if (threadIdx.x == 0) {
+            // (J^T J + lm diag) delta = J^T r, by Cramer's rule on the 3x3 system
+            const double a00 = v[0] * (1 + lm), a11 = v[3] * (1 + lm), a22 = v[5] * (1 + lm);
+            const double a01 = v[1], a02 = v[2], a12 = v[4];
+            const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) + a02 * (a01 * a12 - a11 * a02);
+            const double b0 = v[6], b1 = v[7], b2 = v[8];
+            const double d0 = (b0 * (a11 * a22 - a12 * a12) - a01 * (b1 * a22 - a12 * b2) + a02 * (b1 * a12 - a11 * b2)) / det;
+            const double d1 = (a00 * (b1 * a22 - a12 * b2) - b0 * (a01 * a22 - a12 * a02) + a02 * (a01 * b2 - b1 * a02)) / det;
+            const double d2 = (a00 * (a11 * b2 - b1 * a12) - a01 * (a01 * b2 - b1 * a02) + b0 * (a01 * a12 - a11 * a02)) / det;
+            s_p[0] = A + d0; s_p[1] = mu + d1; s_p[2] = sg + d2;
+            s_done = (fabs(d0) <= 1e-14 * fabs(A) && fabs(d1) <= 1e-14 * (fabs(mu) + sg) && fabs(d2) <= 1e-14 * sg) ? 1 : 0;
+        }
+        __syncthreads();
+        const double nA = s_p[0], nm = s_p[1], ns = fabs(s_p[2]);
+        const int done = s_done;
+        const double c1 = cost(nA, nm, ns);
+        if (c1 <= c0) { A = nA; mu = nm; sg = ns; c0 = c1; lm = fmax(lm * 0.1, 1e-15); }
+        else lm *= 10.0;
+        if (done || lm > 1e12) break;
+    }
+    if (threadIdx.x == 0) {
+        out[(int64_t)O_SIGMA_LSQ * s + w] = sg;
+        out[(int64_t)O_GAMMA2_LSQ * s + w] = P.k * sg * sg / P.kT;
+    }
+}
+
+// Eq. 13 with gamma_i^2 from the fitted sigma_i, <x_i> the sample mean.
+__global__ void k_gauss_fit_profile(const DevProblem *__restrict__ probs, char *__restrict__ ws) {
+    const DevProblem &P = probs[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    const int s = P.n_windows;
+    double *out = dptr(ws, P.off_out);
+    const double *lam = dptr(ws, P.off_lambda);
+    double g = 0.0;
+    out[(int64_t)O_DF_GAUSS_LSQ * s] = 0.0;
+    for (int j = 1; j < s; ++j) {
+        const double dl = lam[j] - lam[j - 1];
+        const double mean = out[(int64_t)O_XI_MEAN * s + j - 1];
+        const double g2 = out[(int64_t)O_GAMMA2_LSQ * s + j - 1];
+        g += P.k * dl * (lam[j - 1] - mean) + 0.5 * P.k * dl * dl * (1.0 - g2);
+        out[(int64_t)O_DF_GAUSS_LSQ * s + j] = g;
+    }
+}
+
+hipError_t launch_estimators(const DevProblem *d_probs, int n_probs, char *ws, int max_windows, hipStream_t stream) {
     hipLaunchKernelGGL(k_estimators, dim3(n_probs), dim3(256), 0, stream, d_probs, ws);
+    hipLaunchKernelGGL(k_gauss_fit, dim3(max_windows, n_probs), dim3(256), 0, stream, d_probs, ws);
+    hipLaunchKernelGGL(k_gauss_fit_profile, dim3(n_probs), dim3(64), 0, stream, d_probs, ws);
     return hipGetLastError();
 }
 

@@ -463,6 +463,9 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
     put(out->dF_unc, o, F(O_DF_UNC), s);
     put(out->dF_rev, o, F(O_DF_REV), s);
     put(out->dF_fluct_literal, o, F(O_DF_FLUCT_LIT), s);
+    put(out->sigma_lsq, o, F(O_SIGMA_LSQ), s);
+    put(out->gamma2_lsq, o, F(O_GAMMA2_LSQ), s);
+    put(out->dF_gauss_lsq, o, F(O_DF_GAUSS_LSQ), s);
     put(out->dF_gauss_literal, o, F(O_DF_GAUSS_LIT), s);
     const bool appc = d.w_half_bins > 0;
     if (appc) {
@@ -579,7 +582,7 @@ ppp_status do_finalize(ppp_handle *h, hipStream_t st) {
     }
     HIPCHK(h, hipEventRecord(h->ev[2], st));
     HIPCHK(h, launch_reduce(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_blocks, st));
-    HIPCHK(h, launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, st));
+    HIPCHK(h, launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, st));
     HIPCHK(h, hipEventRecord(h->ev[3], st));
     HIPCHK(h, launch_appc(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_m, st));
     HIPCHK(h, hipEventRecord(h->ev[4], st));
@@ -740,7 +743,7 @@ static ppp_status batch_capture(ppp_handle *h) {
         if (e == hipSuccess) e = hipStreamWaitEvent(h->cap, h->side_ev[gi + 1], 0);
     }
     if (e == hipSuccess) e = launch_reduce(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_blocks, h->cap);
-    if (e == hipSuccess) e = launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, h->cap);
+    if (e == hipSuccess) e = launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->cap);
     if (e == hipSuccess) e = launch_appc(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_m, h->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(h->cap, &g);

@@ -148,6 +148,10 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
     for key in ("kish_frac", "overlap_ovl", "dlambda_over_sigma", "dlambda_over_reach"):
         assert np.allclose(res[key], ref[key][:s - 1], rtol=1e-9, atol=1e-12), key
     assert np.array_equal(res["criterion_ok"].astype(bool), ref["criterion_ok"][:s - 1])
+    # least-squares Gaussian fits: two solvers (GPU Levenberg-Marquardt, MINPACK) at one minimum
+    for key in ("sigma_lsq", "gamma2_lsq"):
+        assert np.allclose(res[key], ref[key], rtol=1e-6, atol=1e-12, equal_nan=True), (key, res[key], ref[key])
+    assert np.allclose(res["dF_gauss_lsq"], ref["dF_gauss_lsq"], rtol=1e-6, atol=1e-6, equal_nan=True)
     if int(prob.get("w_half_bins", 0)) > 0:
         assert np.max(np.abs(res["work_hist"] - ref["work_hist"])) < 1e-12
         for key in ("dF_je_hist", "dF_je_hist_mid", "dF_je_hist_literal"):

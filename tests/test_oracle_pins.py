@@ -702,3 +702,49 @@ def test_crooks_relation_on_exact_gaussian_windows():
         assert 0.0 < rev["crooks_ovl"][j] <= 1.0
     # the overlap shrinks as the path gets longer
     assert np.all(np.diff(rev["crooks_ovl"][1:]) < 0)
+
+
+# ---------------------------------------------------------------------------
+# sigma_i by least-squares fitting (Sec. IV A)
+
+def test_gauss_fit_recovers_an_exact_gaussian():
+    """Histogram values that are exactly a Gaussian density at the bin centres:
+    the least-squares fit returns its amplitude, centre and width."""
+    dx, x0, K, n = 0.01, -2.0, 500, 10 ** 6
+    x = x0 + (np.arange(K) + 0.5) * dx
+    mu, sg = 0.137, 0.2315
+    dens = np.exp(-(x - mu) ** 2 / (2 * sg ** 2)) / (sg * np.sqrt(2 * np.pi))
+    A, m, s = estimators.gauss_fit(dens * n * dx, n, x0, dx, mu + 0.03, sg * 1.2)
+    assert abs(m - mu) < 1e-10 and abs(s - sg) < 1e-10 and abs(A - 1 / (sg * np.sqrt(2 * np.pi))) < 1e-9
+
+
+def test_gauss_fit_is_a_least_squares_minimum():
+    """On a skewed histogram the fitted (A, mu, sigma) is a stationary point of
+    the stated objective (central differences of the summed squared residual
+    vanish to rounding) and beats the moments it starts from."""
+    rng = np.random.default_rng(8)
+    smp = np.concatenate([rng.normal(0.0, 0.3, 40000), rng.normal(0.6, 0.2, 15000)])
+    dx, x0, K = 0.02, -2.0, 200
+    counts = np.bincount(np.floor((smp - x0) / dx).astype(int), minlength=K)[:K]
+    n = smp.size
+    A, m, s = estimators.gauss_fit(counts, n, x0, dx, smp.mean(), smp.std(ddof=1))
+    x = x0 + (np.arange(K) + 0.5) * dx
+    y = counts / (n * dx)
+
+    def cost(p):
+        return np.sum((y - p[0] * np.exp(-(x - p[1]) ** 2 / (2 * p[2] ** 2))) ** 2)
+    p = np.array([A, m, s])
+    for q in range(3):
+        h = 1e-6 * max(abs(p[q]), 1e-3)
+        e = np.zeros(3); e[q] = h
+        grad = (cost(p + e) - cost(p - e)) / (2 * h)
+        assert abs(grad) < 1e-6 * (1 + cost(p) / abs(p[q])), (q, grad)
+    start = np.array([1 / (smp.std(ddof=1) * np.sqrt(2 * np.pi)), smp.mean(), smp.std(ddof=1)])
+    assert cost(p) < cost(start)
+    # the same minimum as MINPACK's Levenberg-Marquardt from the same start
+    from scipy.optimize import least_squares
+    ref = least_squares(lambda q: y - q[0] * np.exp(-(x - q[1]) ** 2 / (2 * q[2] ** 2)), start, method="lm",
+                        xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    assert np.allclose([A, m, s], [ref.x[0], ref.x[1], abs(ref.x[2])], rtol=1e-9)
+    # a window without enough samples has no fit
+    assert all(np.isnan(estimators.gauss_fit(np.zeros(5), 2, 0.0, 1.0, 0.0, 1.0)))
