@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 KEYS = ("dF_je", "dF_fluct", "dF_gauss", "dF_je_se", "xi_mean", "xi_std", "n_samples", "xi_hist", "dF_je_hist",
-        "work_hist", "overlap_ovl", "kish_frac")
+        "work_hist", "overlap_ovl", "kish_frac", "work_hist_rev", "dF_crooks", "sigma_lsq", "dF_gauss_lsq",
+        "dF_je_hist_literal")
 
 
 def _say(*a):
@@ -74,6 +75,32 @@ def test_batch_matches_single_runs_on_every_replay(precision):
                 r = ppp.ppp_batch_get_result(h, p, i)
                 for key in KEYS:
                     assert _equal(r[key], singles[i][key], key), (replay, i, key)
+    finally:
+        ppp.ppp_destroy(h)
+
+
+def test_batch_with_free_ensembles_matches_single_runs():
+    """Problems that also sample the unrestrained ensemble (one more window of
+    replicas each) mixed with plain ones in one batch: every output, the
+    turn-on values included, equals the problem's own single run."""
+    probs = _small_batch(6, seed=13, precision="fp32")
+    for i, p in enumerate(probs):
+        p["free_ensemble"] = i % 2 == 0
+    _say(f"case batch free ensembles: N = {[p['n_beads'] for p in probs]}")
+    singles = [ppp.run(p)[0] for p in probs]
+    h = ppp.ppp_batch_create(probs)
+    try:
+        ws = ppp.workspace(h)
+        for replay in range(2):
+            ppp.ppp_run(h, ws)
+            torch.cuda.synchronize()
+            for i, p in enumerate(probs):
+                r = ppp.ppp_batch_get_result(h, p, i)
+                for key in KEYS + ("G", "G_se", "xi_hist_free"):
+                    assert _equal(r[key], singles[i][key], key), (replay, i, key)
+                for key, v in singles[i]["turn_on"].items():
+                    assert np.array_equal(r["turn_on"][key], v, equal_nan=True), (replay, i, key)
+                assert np.isfinite(r["turn_on"]["eq6_first"]) == p["free_ensemble"]
     finally:
         ppp.ppp_destroy(h)
 
