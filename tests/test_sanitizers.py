@@ -6,7 +6,6 @@ built kernels but touching no GPU.  Device code is never instrumented."""
 import os
 import shutil
 import subprocess
-import sys
 
 import pytest
 
@@ -32,8 +31,10 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers(tmp_path):
 
 
 def _kernel_objects():
-    sys.path.insert(0, PKG)
-    import build  # noqa: E402  (the package's build script)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("ppp_pkg_build", os.path.join(PKG, "build.py"))
+    build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(build)
     names = [f"shape_{t}_{g}x{b}.hip.o" for g, b in build.shapes() for t in ("float", "double")]
     names += ["ppp_sim.hip.o", "ppp_reduce.hip.o", "ppp_mlp.hip.o"]
     return [os.path.join(PKG, "_build", n) for n in names]
