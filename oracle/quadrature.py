@@ -145,3 +145,17 @@ def harmonic_turn_on_closed_form(kappa, k, kT, lam):
     kT/2 ln((kappa + k)/kappa) + kappa k lambda^2 / (2 (kappa + k))."""
     lam = np.asarray(lam, dtype=np.float64)
     return 0.5 * kT * np.log((kappa + k) / kappa) + kappa * k * lam ** 2 / (2.0 * (kappa + k))
+
+
+def chain2_turn_on(lam, k, kT, k_bond, r0, lo=1e-6, hi=None, n_panels=2000):
+    """Turn-on free energy dF(lambda, k) = -kT ln [Z(lambda, k) / Z(0)] of the two-bead
+    chain (bead 0 fixed, xi = |r_1|), both partition functions as radial integrals
+    int 4 pi r^2 exp(-beta [k_b/2 (r - r0)^2 (+ k/2 (r - lambda)^2)]) dr."""
+    beta = 1.0 / kT
+    lam_arr = np.atleast_1d(np.asarray(lam, dtype=np.float64))
+    if hi is None:
+        hi = max(r0, lam_arr.max()) + 12.0 * np.sqrt(kT / min(k_bond, k)) + 1.0
+    r, w = _panels(lo, hi, n_panels)
+    lz0, _, _ = _moments(r, w, 2.0 * np.log(r) - beta * 0.5 * k_bond * (r - r0) ** 2)
+    F, _, _ = chain2(lam_arr, k, kT, k_bond, r0, lo, hi, n_panels)
+    return F + kT * lz0

@@ -748,3 +748,26 @@ def test_gauss_fit_is_a_least_squares_minimum():
     assert np.allclose([A, m, s], [ref.x[0], ref.x[1], abs(ref.x[2])], rtol=1e-9)
     # a window without enough samples has no fit
     assert all(np.isnan(estimators.gauss_fit(np.zeros(5), 2, 0.0, 1.0, 0.0, 1.0)))
+
+
+def test_turn_on_two_bead_chain_against_radial_quadrature():
+    """The chain path of the unrestrained ensemble (BAOAB with the restraint off):
+    for two beads, Eq. 5 and Eq. 6 at both ends against the ratio of the two radial
+    partition functions.  The bond (k_b = 100) is stiffer than the restraint (k = 20),
+    so the restrained windows cover the free density and Eq. 5's average has finite
+    variance."""
+    p = ppp_inputs.config_chain_small(2, n_replicas=64, n_steps=6000, n_windows=4, precision="fp64")
+    p["lambda"] = [0.8, 0.95, 1.1, 1.25]
+    p.update({"free_ensemble": True, "w_half_bins": 0, "n_blocks": 16})
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    on = r["turn_on"]
+    exact = quadrature.chain2_turn_on([0.8, 1.25], 20.0, 1.0, 100.0, 1.0)
+    for key, want in (("eq5_first", exact[0]), ("eq6_first", exact[0]), ("eq5_last", exact[1]), ("eq6_last", exact[1])):
+        assert abs(on[key] - want) < 4.0 * on[key + "_se"] + 0.005, (key, on[key], want, on[key + "_se"])
+    assert abs(on["eq10_log"]) < 4.0 * on["eq10_log_se"] + 0.005
+    # the free ensemble's end-to-end distance is the bond length distribution
+    r_grid = np.linspace(0.5, 1.5, 20001)
+    dens = r_grid ** 2 * np.exp(-50.0 * (r_grid - 1.0) ** 2)
+    mean_exact = np.sum(r_grid * dens) / np.sum(dens)
+    assert abs(on["free_mean"] - mean_exact) < 0.01
