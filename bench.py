@@ -26,11 +26,11 @@ FP64_PEAK = 78.6e12
 # HBM traffic of one launch of the simulation kernel, from two rocprofv3 --pmc runs of
 # this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
 # same counter reads for a 1 GiB device-to-device copy in the same run (--pmc-copy-mib
-# 1024: FETCH_SIZE reads 524308 KiB -> x2.0, WRITE_SIZE 1048576 KiB -> x1.0).  A record
-# holds only while the kernel sources hash to the digest it was taken on.
+# 1024: FETCH_SIZE reads 529747.5 KiB -> x1.9794, WRITE_SIZE 1059107.1 KiB -> x0.9901).
+# A record holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain10": {"sources_sha1": "f0adea1aa7205a41819ce284bbdf6677d8bdc068", "kernel": "sim_chain<float,5,2>",
-                "fetch_kib": 177.5, "fetch_scale": 2.0, "write_kib": 10146.125, "write_scale": 1.0},
+    "chain10": {"sources_sha1": "07a05ed8a90fa978f129f3f0d9c7631fec9ac261", "kernel": "sim_chain<float,5,2>",
+                "fetch_kib": 175.0, "fetch_scale": 1.9794, "write_kib": 10146.03125, "write_scale": 0.9901},
 }
 KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
                   "ppp_launch.hpp")

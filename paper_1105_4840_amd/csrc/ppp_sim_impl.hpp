@@ -269,6 +269,7 @@ struct ChainForce {
                                                     const T (&bz)[B], T (&fx)[B], T (&fy)[B], T (&fz)[B],
                                                     T (&gx)[B], T (&gy)[B], T (&gz)[B], int ia0, int ib0,
                                                     T lA, T lB, T rc2, double &e_lj) {
+#pragma clang fp contract(on)
 #pragma unroll
         for (int b1 = 0; b1 < B; ++b1) {
 #pragma unroll
@@ -298,6 +299,11 @@ struct ChainForce {
     __device__ __forceinline__ static void compute(const DevProblem &P, int g, int gbase, T centre, T kr,
                                                    const T (&px)[B], const T (&py)[B], const T (&pz)[B],
                                                    T (&fx)[B], T (&fy)[B], T (&fz)[B], double *e) {
+        // Products are fused into adds only inside one expression, never across
+        // statements: the forces then round the same way wherever this is
+        // inlined, so the forces recomputed from the stored state when a run
+        // resumes equal the ones the uninterrupted run carried.
+#pragma clang fp contract(on)
         const int N = P.n_beads;
         const int i0 = g * B;
         const bool solo = gbase + G > 64;
@@ -306,6 +312,7 @@ struct ChainForce {
         double e_lj = 0.0, e_bond = 0.0, e_ang = 0.0, e_res = 0.0;
 #pragma unroll
         for (int b = 0; b < B; ++b) { fx[b] = 0; fy[b] = 0; fz[b] = 0; }
+        T hpx = 0, hpy = 0, hpz = 0, hnx = 0, hny = 0, hnz = 0;   // halo beads of the bonded terms
 
         // ---- Lennard-Jones: pairs inside the lane (|i-j| > 2 by construction) ----
 #pragma unroll
@@ -341,8 +348,10 @@ struct ChainForce {
 #pragma unroll
                 for (int b = 0; b < B; ++b) { qx[b] = pull_f(src, qx[b]); qy[b] = pull_f(src, qy[b]); qz[b] = pull_f(src, qz[b]); }
             };
-            // round 1
+            // round 1; its j-beads are the previous lane's, whose last bead is also
+            // the halo bead of the bonded terms below
             pull_q();
+            hpx = qx[B - 1]; hpy = qy[B - 1]; hpz = qz[B - 1];
             {
                 double e_r = 0.0;
                 const int jb = ((g + G - 1) % G) * B;
@@ -385,15 +394,16 @@ struct ChainForce {
 
         // ---- bonded terms, each computed once ----
         // Local slots 0..B+1: slot 0 is the previous lane's last bead, slots 1..B
-        // the owned beads, slot B+1 the next lane's first bead.  A lane takes the
-        // bonds that start at an owned bead and the angles centred on owned
-        // beads; the forces these put on the two halo beads are read back by the
-        // lanes that own them.
-        T hpx = 0, hpy = 0, hpz = 0, hnx = 0, hny = 0, hnz = 0;   // halo beads
+        // the owned beads, slot B+1 the next lane's first bead; bond t joins slot
+        // t to slot t+1.  A lane takes the bonds that start at an owned bead and
+        // the angles centred on owned beads.  These terms depend on the beads
+        // only through the bond vectors b_t = x_{t+1} - x_t, so their gradients
+        // are gathered per bond, D_t = dU/db_t, and the force on slot t is
+        // D_t - D_{t-1}; the two halo beads get D_0 and -D_B, which the lanes
+        // owning them read back.
         const int prev = solo ? me : gbase + (g > 0 ? g - 1 : 0);
         const int next = solo ? me : gbase + (g + 1 < G ? g + 1 : G - 1);
         if constexpr (G > 1) {
-            hpx = pull_f(prev, px[B - 1]); hpy = pull_f(prev, py[B - 1]); hpz = pull_f(prev, pz[B - 1]);
             hnx = pull_f(next, px[0]); hny = pull_f(next, py[0]); hnz = pull_f(next, pz[0]);
         }
         const T kb = (T)P.k_bond, r0 = (T)P.r0, kth = (T)P.k_angle;
@@ -402,13 +412,8 @@ struct ChainForce {
             else if (t <= B) { x = px[t - 1]; y = py[t - 1]; z = pz[t - 1]; }
             else { x = hnx; y = hny; z = hnz; }
         };
-        T qpx = 0, qpy = 0, qpz = 0, qnx = 0, qny = 0, qnz = 0;   // forces on the halo beads
-        auto add = [&](int t, T gx_, T gy_, T gz_) {
-            if (t == 0) { qpx += gx_; qpy += gy_; qpz += gz_; }
-            else if (t <= B) { fx[t - 1] += gx_; fy[t - 1] += gy_; fz[t - 1] += gz_; }
-            else { qnx += gx_; qny += gy_; qnz += gz_; }
-        };
-        T ax = 0, ay = 0, az = 0, ail = 0;   // previous bond (t-1 -> t) and its inverse length
+        T Dx[B + 1], Dy[B + 1], Dz[B + 1];
+        T ux = 0, uy = 0, uz = 0, ail = 0;   // previous bond (t-1 -> t): unit vector, inverse length
         bool avalid = false;
 #pragma unroll
         for (int t = 0; t <= B; ++t) {
@@ -421,37 +426,39 @@ struct ChainForce {
             // a bond outside the chain gets unit length so its masked terms stay finite
             T bl, bil;
             len_inv(bvalid ? bx * bx + by * by + bz * bz : (T)1, bl, bil);
-            if (t >= 1) {
+            const T vx = bx * bil, vy = by * bil, vz = bz * bil;
+            if (t == 0) {
+                Dx[0] = 0; Dy[0] = 0; Dz[0] = 0;
+            } else {
                 // bond (t, t+1), k_b/2 (|b| - r0)^2: dU/db = k_b (|b| - r0) b/|b|
-                T gsc = kb * (bl - r0) * bil;
+                T gsc = kb * (bl - r0);
                 gsc = bvalid ? gsc : (T)0;
-                add(t, gsc * bx, gsc * by, gsc * bz);
-                add(t + 1, -gsc * bx, -gsc * by, -gsc * bz);
+                Dx[t] = gsc * vx; Dy[t] = gsc * vy; Dz[t] = gsc * vz;
                 if (ENERGY && bvalid) e_bond += 0.5 * (double)(kb * (bl - r0) * (bl - r0));
-                // angle centred on slot t between bond a (t-1 -> t) and bond b (t -> t+1)
+                // angle centred on slot t between bond a (t-1 -> t) and bond b (t -> t+1),
+                // unit vectors u and v, c = u.v:
+                // dU/da = k (c u - v)/|a|, dU/db = k (c v - u)/|b|
                 const bool valid = avalid && bvalid;
-                const T iab = ail * bil;
-                const T c = (ax * bx + ay * by + az * bz) * iab;
-                const T ca = c * ail * ail, cb = c * bil * bil;
+                const T c = ux * vx + uy * vy + uz * vz;
                 const T kk = valid ? kth : (T)0;
-                // dU/da = -k (b/(|a||b|) - c a/|a|^2), dU/db = -k (a/(|a||b|) - c b/|b|^2)
-                const T s_ab = -kk * iab, s_a = kk * ca, s_b = kk * cb;
-                const T dax = s_ab * bx + s_a * ax, day = s_ab * by + s_a * ay, daz = s_ab * bz + s_a * az;
-                const T dbx = s_ab * ax + s_b * bx, dby = s_ab * ay + s_b * by, dbz = s_ab * az + s_b * bz;
-                add(t - 1, dax, day, daz);
-                add(t, dbx - dax, dby - day, dbz - daz);
-                add(t + 1, -dbx, -dby, -dbz);
+                const T sa = kk * ail, sb = kk * bil;
+                Dx[t - 1] += sa * (c * ux - vx); Dy[t - 1] += sa * (c * uy - vy); Dz[t - 1] += sa * (c * uz - vz);
+                Dx[t] += sb * (c * vx - ux); Dy[t] += sb * (c * vy - uy); Dz[t] += sb * (c * vz - uz);
                 if (ENERGY && valid) e_ang += (double)(kth * ((T)1 - c));
             }
-            ax = bx; ay = by; az = bz; ail = bil; avalid = bvalid;
+            ux = vx; uy = vy; uz = vz; ail = bil; avalid = bvalid;
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            fx[b] += Dx[b + 1] - Dx[b]; fy[b] += Dy[b + 1] - Dy[b]; fz[b] += Dz[b + 1] - Dz[b];
         }
         if constexpr (G > 1) {
-            // the next lane's slot-0 force is on our last bead, the previous lane's
-            // slot-(B+1) force on our first
-            const T lx = pull_f(next, qpx), ly = pull_f(next, qpy), lz = pull_f(next, qpz);
-            const T fx0 = pull_f(prev, qnx), fy0 = pull_f(prev, qny), fz0 = pull_f(prev, qnz);
+            // our last bead is the next lane's slot 0 (force D_0 there), our first
+            // bead the previous lane's slot B+1 (force -D_B there)
+            const T lx = pull_f(next, Dx[0]), ly = pull_f(next, Dy[0]), lz = pull_f(next, Dz[0]);
+            const T fx0 = pull_f(prev, Dx[B]), fy0 = pull_f(prev, Dy[B]), fz0 = pull_f(prev, Dz[B]);
             if (g + 1 < G) { fx[B - 1] += lx; fy[B - 1] += ly; fz[B - 1] += lz; }
-            if (g > 0) { fx[0] += fx0; fy[0] += fy0; fz[0] += fz0; }
+            if (g > 0) { fx[0] -= fx0; fy[0] -= fy0; fz[0] -= fz0; }
         }
 
         // ---- restraint k/2 (xi - centre)^2 on the pulled end ----

@@ -415,9 +415,9 @@ def test_checkpoint_resume_is_bit_identical():
 
 
 def test_advancing_in_uneven_chunks_matches_one_run():
-    """The chain noise is drawn per group of four steps with deviates carried
-    between steps; advances that stop at every position inside a group must
-    rebuild the carried deviates and give the single run's results exactly."""
+    """A launch carries positions and velocities over and recomputes the forces
+    from them; advances of 1 to 13 steps must give the single run's results
+    exactly, so those recomputed forces have to round as the carried ones did."""
     _say("case uneven chunks")
     for precision in ("fp32", "fp64"):
         prob = ppp_inputs.config_chain_small(10, n_replicas=30, n_steps=240, n_windows=3, precision=precision)
