@@ -261,6 +261,8 @@ __global__ __launch_bounds__(WG) void sim_1d(const DevProblem *__restrict__ prob
 // ===========================================================================
 template <typename T, int G, int B, bool ENERGY>
 struct ChainForce {
+    // groups of at most 6 lanes run no Newton-3 rounds beyond round 2
+    static constexpr bool kHaloFromRound1 = G > 1 && (G - 1) / 2 <= 2;
 
     // Lennard-Jones between bead sets a (owned) and b; N3: also accumulate reaction on b.
     template <bool N3, bool MASK>
@@ -349,9 +351,11 @@ struct ChainForce {
                 for (int b = 0; b < B; ++b) { qx[b] = pull_f(src, qx[b]); qy[b] = pull_f(src, qy[b]); qz[b] = pull_f(src, qz[b]); }
             };
             // round 1; its j-beads are the previous lane's, whose last bead is also
-            // the halo bead of the bonded terms below
+            // the halo bead of the bonded terms below.  Small groups keep it from
+            // here; in groups with a loop of further rounds, three more registers
+            // live across that loop cost more than pulling the bead again.
             pull_q();
-            hpx = qx[B - 1]; hpy = qy[B - 1]; hpz = qz[B - 1];
+            if constexpr (kHaloFromRound1) { hpx = qx[B - 1]; hpy = qy[B - 1]; hpz = qz[B - 1]; }
             {
                 double e_r = 0.0;
                 const int jb = ((g + G - 1) % G) * B;
@@ -404,6 +408,9 @@ struct ChainForce {
         const int prev = solo ? me : gbase + (g > 0 ? g - 1 : 0);
         const int next = solo ? me : gbase + (g + 1 < G ? g + 1 : G - 1);
         if constexpr (G > 1) {
+            if constexpr (!kHaloFromRound1) {
+                hpx = pull_f(prev, px[B - 1]); hpy = pull_f(prev, py[B - 1]); hpz = pull_f(prev, pz[B - 1]);
+            }
             hnx = pull_f(next, px[0]); hny = pull_f(next, py[0]); hnz = pull_f(next, pz[0]);
         }
         const T kb = (T)P.k_bond, r0 = (T)P.r0, kth = (T)P.k_angle;
