@@ -269,7 +269,7 @@ def test_oracle_je_matches_double_well_quadrature():
     exact = F - F[0]
     z = (r["dF_je"] - exact)[1:] / r["dF_je_se"][1:]
     assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 4.0
-    # dF_fluct is biased by construction (survey of the exact moments: about -2 kT at the end)
+    # dF_fluct is biased by construction (the exact moments put it about -2 kT off at the end)
     fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
     assert abs((r["dF_fluct"][-1] - fl[-1]) / r["dF_fluct_se"][-1]) < 3.5
     assert fl[-1] < -1.9
