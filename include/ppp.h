@@ -212,8 +212,9 @@ typedef struct {
      * x_i distribution): the Gaussian A exp(-(x - mu)^2 / (2 sigma^2)) closest in
      * least squares to the histogram density count_b / (n xi_bin) at the bin
      * centres (Levenberg-Marquardt from the sample moments; NaN for windows with
-     * fewer than 3 samples or fewer than 3 non-empty bins); gamma_i^2 = k sigma_i^2 / kT from it; and Eq. 13 with
-     * that gamma_i^2 and the sample means */
+     * fewer than 3 samples or fewer than 3 non-empty bins); gamma_i^2 =
+     * k sigma_i^2 / kT from it; and Eq. 13 with that gamma_i^2 and the sample
+     * means */
     double *sigma_lsq, *gamma2_lsq, *dF_gauss_lsq;
 } ppp_result;
 
