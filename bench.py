@@ -7,7 +7,7 @@ distributions, with inputs resident in device memory.  `value` is the number
 of replica-steps (one integrator step of one replica, with its force
 evaluation, noise, sampling and accumulation) per second of wall time.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the protocol runs on one GPU here.
 """
 import argparse
 import json
@@ -29,7 +29,7 @@ FP64_PEAK = 78.6e12
 # 1024: FETCH_SIZE reads 529747.5 KiB -> x1.9794, WRITE_SIZE 1059107.1 KiB -> x0.9901).
 # A record holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain10": {"sources_sha1": "dd6b1e18cdd24c17603cbe4d85c6607b28c4b6d3", "kernel": "sim_chain<float,5,2>",
+    "chain10": {"sources_sha1": "04fdcc61e43361cc039f1648b793919ae0c4150d", "kernel": "sim_chain<float,5,2>",
                 "fetch_kib": 175.0, "fetch_scale": 1.9794, "write_kib": 10146.03125, "write_scale": 0.9901},
 }
 KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
@@ -95,7 +95,23 @@ def cpu_baseline(prob, target_seconds):
     rs = reps * steps_total
     return {"value": rs / el, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(p['lambda'])} windows x {reps} replicas x {p['n_steps']} steps "
-                      f"({rs:.3g} replica-steps, {el:.1f} s, fp64 C, OpenMP over replicas)"}
+                      f"({rs:.3g} replica-steps, {el:.1f} s, fp64 C, OpenMP over replicas)",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical CPUs visible to this process, as the oracle timing's context."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def placement_study(args):
@@ -301,8 +317,8 @@ def main():
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the protocol on one GPU; --gpus must be 1 "
-              "(the path shards by windows and replica blocks, see the design notes)", file=sys.stderr)
+        print("bench.py: the protocol runs on one GPU here; --gpus must be 1 (windows and replica "
+              "blocks are independent, but no multi-GPU launch is implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -46,7 +46,7 @@ typedef enum {
     PPP_E_DEVICE = 3,        /* a HIP call failed; ppp_last_error has the HIP message */
     PPP_E_NUMERICAL = 4,     /* more than 1% of the replicas of some window were frozen */
     PPP_E_STATE = 5,         /* call out of order (e.g. result before run) */
-    PPP_E_UNSUPPORTED = 6    /* valid request this build does not implement */
+    PPP_E_UNSUPPORTED = 6    /* valid request this library does not implement */
 } ppp_status;
 
 typedef enum { PPP_MODEL_1D = 0, PPP_MODEL_CHAIN = 1 } ppp_model;

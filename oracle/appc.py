@@ -6,7 +6,7 @@ the previous window: a work bin w of Omega_{j-1} combined with an x bin b of
 rho_{j-1} lands in bin floor(W/dW) with W = w dW + dW_{j-1}(x_b), and carries
 probability rho_{j-1}(b) Omega_{j-1}(w).
 
-Readings taken here (each also listed with its reason in the design notes):
+Readings taken here where the appendix leaves a choice:
 
 * the per-step increment is dlambda_i = lambda_{i+1} - lambda_i (not
   (lambda_s - lambda_1)/s);

@@ -1,6 +1,6 @@
 // Chain kernel shapes compiled into libppp: X(G lanes per replica, B beads per lane).
 // Only shapes whose kernels need no scratch memory in either precision are
-// built (the build checks this); more beads per lane spill registers.
+// built (build.py checks this); more beads per lane spill registers.
 // 1 <= G <= 64 (a wavefront holds 64 / G groups; 64 mod G lanes stay idle);
 // B >= 2 whenever G > 1 (Lennard-Jones exclusions, |i-j| <= 2, are masked only
 // between neighbouring lanes).
