@@ -11,6 +11,7 @@ Prints one JSON line.  --gpus N with N > 1 exits: the protocol runs on one GPU h
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -79,22 +80,42 @@ WORKLOADS = {
 
 
 def cpu_baseline(prob, target_seconds):
-    """The fp64 oracle on a bounded sample of the same workload: every window, the full
-    per-replica step count, fewer replicas."""
-    import numpy as np
+    """The fp64 oracle on a bounded sample of the same workload: every window and the
+    full per-replica step count with fewer replicas; where even two replicas would run
+    well past the target time (the long chains), two replicas and fewer steps, with
+    the equilibration and pulling phases scaled alike."""
     import oracle
-    p = dict(prob)
-    steps_total = len(p["lambda"]) * p["n_steps"]
-    # calibrate on a tiny sample, then size the measured one
-    p["n_replicas"] = 2
-    t0 = time.time(); _, _, threads = oracle.run(p); t_cal = max(time.time() - t0, 1e-3)
-    rate = 2 * steps_total / t_cal
-    reps = int(max(2, min(prob["n_replicas"], target_seconds * rate / steps_total)))
-    p["n_replicas"] = reps
+    n_win = len(prob["lambda"])
+
+    def sized(reps, steps):
+        p = dict(prob)
+        p["n_replicas"] = int(reps)
+        if steps < prob["n_steps"]:
+            p["n_steps"] = int(steps)
+            p["n_equil"] = int(steps) * int(prob["n_equil"]) // int(prob["n_steps"])
+            if int(prob.get("n_pull", 0)) > 0:
+                p["n_pull"] = max(1, int(steps) * int(prob["n_pull"]) // int(prob["n_steps"]))
+        return p
+
+    def parallel(items, threads):   # items run at once on average (dynamic schedule, equal items)
+        return items / math.ceil(items / max(1, threads))
+
+    # calibrate on a short sample, then size the measured one
+    cal_steps = min(int(prob["n_steps"]), 4000)
+    t0 = time.time(); _, _, used = oracle.run(sized(2, cal_steps)); t_cal = max(time.time() - t0, 1e-3)
+    per_item = 2 * n_win * cal_steps / t_cal / parallel(2 * n_win, used)   # replica-steps/s per thread
+    steps = int(prob["n_steps"])
+    reps = int(target_seconds * per_item * used / (n_win * steps))
+    if reps < 2:
+        reps = 2
+        fit = target_seconds * per_item * parallel(2 * n_win, used) / (2 * n_win)
+        steps = int(max(min(steps, 1000), min(steps, fit)))
+    reps = min(reps, int(prob["n_replicas"]))
+    p = sized(reps, steps)
     t0 = time.time(); xi, kept, threads = oracle.run(p); el = time.time() - t0
-    rs = reps * steps_total
+    rs = reps * n_win * p["n_steps"]
     return {"value": rs / el, "unit": "replica-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(p['lambda'])} windows x {reps} replicas x {p['n_steps']} steps "
+            "sample": f"{n_win} windows x {reps} replicas x {p['n_steps']} steps "
                       f"({rs:.3g} replica-steps, {el:.1f} s, fp64 C, OpenMP over replicas)",
             "host": host_cpu()}
 
