@@ -533,3 +533,34 @@ def test_every_kernel_shape_fp64_trajectory_and_forces(shape, tmp_path, monkeypa
         xc = conf[c].astype(np.float32).astype(np.float64)
         _, _, fr = oracle.chain_forces(p32, xc, 0.4 * n)
         assert np.linalg.norm(f[c, 1:] - fr[1:]) <= 1e-5 * np.linalg.norm(fr[1:])
+
+
+@pytest.mark.parametrize("shape", _shapes(), ids=lambda s: f"{s[0]}x{s[1]}")
+def test_every_kernel_shape_resumes_bit_exactly(shape, tmp_path, monkeypatch):
+    """The uneven-chunk check for every compiled shape, forced through the shape
+    table, in both precisions: the forces each advance recomputes from the stored
+    state must round as the ones the uninterrupted run carried, whatever the
+    compiler does with the inlined force code of that shape."""
+    G, B = shape
+    n = max(2, G * B - (B // 2))
+    table = tmp_path / "tune.txt"
+    table.write_text(f"{n} 1 {G} {B}\n{n} 0 {G} {B}\n")
+    monkeypatch.setenv("PPP_TUNE_TABLE", str(table))
+    for precision in ("fp32", "fp64"):
+        _say(f"case resume shape {G}x{B} N={n} {precision}")
+        prob = ppp_inputs.config_chain_small(n, n_replicas=6, n_steps=120, n_windows=3, precision=precision)
+        full, _ = ppp.run(prob)
+        h = ppp.ppp_create(prob)
+        try:
+            ws = ppp.workspace(h)
+            ppp.ppp_begin(h, ws)
+            for k in [1, 2, 3, 5, 7, 13] * 3:
+                ppp.ppp_advance(h, k)
+            ppp.ppp_advance(h, 10 ** 9)
+            ppp.ppp_finalize(h)
+            part = ppp.ppp_get_result(h, prob)
+        finally:
+            ppp.ppp_destroy(h)
+        for key in ("dF_je", "xi_mean", "xi_std", "xi_hist", "n_samples"):
+            assert np.array_equal(full[key], part[key], equal_nan=True), (precision, key)
+
