@@ -311,6 +311,52 @@ def turn_on_study(args):
     print(json.dumps({"study": "turn-on free energy", "rows": rows}), flush=True)
 
 
+def peak_study(args):
+    """Measured ceilings beside the published ones, as context for the roofline
+    fractions (which always use the published peaks): the fp32 FMA issue rate of
+    plain (non-packed) v_fma_f32, the form every kernel here is compiled to, and a
+    device-to-device copy for HBM."""
+    import torch
+    import paper_1105_4840_amd as ppp
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    n_blocks, iters = 16384, 16384
+    out = torch.empty(n_blocks * 256, dtype=torch.float32, device=dev)
+    ppp.ppp_probe_valu(n_blocks, 64, out=out)                  # warm-up
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(5):
+        t0.record(stream)
+        ppp.ppp_probe_valu(n_blocks, iters, out=out, stream=stream)
+        t1.record(stream)
+        t1.synchronize()
+        ms.append(t0.elapsed_time(t1))
+    flops = 16.0 * iters * n_blocks * 256
+    fma = flops / (min(ms) * 1e-3) / 1e12
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    cms = []
+    for _ in range(10):
+        t0.record(stream)
+        dst.copy_(src)
+        t1.record(stream)
+        t1.synchronize()
+        cms.append(t0.elapsed_time(t1))
+    gbs = 2.0 * nbytes / (min(cms) * 1e-3) / 1e9
+    print(json.dumps({
+        "study": "measured ceilings (context; roofline fractions use the published peaks)",
+        "fp32_fma": {"tflops": fma, "ms": min(ms), "flops": flops, "threads": n_blocks * 256, "chains_per_thread": 8,
+                     "published_packed_peak": FP32_PEAK / 1e12, "published_unpacked_rate": FP32_PEAK / 2e12,
+                     "frac_of_unpacked": fma / (FP32_PEAK / 2e12)},
+        "hbm_copy": {"gb_per_s": gbs, "ms": min(cms), "bytes_moved": 2 * nbytes, "published_peak": 8000.0,
+                     "frac": gbs / 8000.0},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +371,7 @@ def main():
     ap.add_argument("--ref-steps", type=int, default=40000)
     ap.add_argument("--sweep", action="store_true", help="tau and k sweep of the 10-bead chain in one batched graph")
     ap.add_argument("--turn-on", action="store_true", help="turn-on free energy study (unrestrained ensemble)")
+    ap.add_argument("--peak", action="store_true", help="measured fp32 FMA and HBM copy rates beside the published peaks")
     ap.add_argument("--min-steps", type=int, default=20000, help="relaxation steps per learned production window")
     ap.add_argument("--sequential", action="store_true",
                     help="run the workload with the sequential pulling protocol (each replica runs the "
@@ -358,6 +405,10 @@ def main():
     if args.turn_on:
         torch.cuda.set_device(0)
         turn_on_study(args)
+        return
+    if args.peak:
+        torch.cuda.set_device(0)
+        peak_study(args)
         return
     fn, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)

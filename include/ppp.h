@@ -314,6 +314,16 @@ ppp_status ppp_trajectory(ppp_handle *h, void *d_workspace, size_t bytes, int32_
 ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n,
                       uint32_t *d_words, double *d_normals, float *d_normals32, void *hip_stream);
 
+/* Vector-ALU issue-rate probe, not part of the protocol: the fp32 FMA rate
+ * the simulation kernels' roofline is read against.  n_blocks workgroups of
+ * 256 threads each run 8 independent chains a <- fma(a, b, c) for iters steps
+ * (16 iters flops per thread), chain k of thread i starting at
+ * ((i + k) mod 1024) 1e-6, and write the sum of the 8 chains to d_out[i]
+ * (device fp32 [n_blocks * 256], caller-owned).  Asynchronous on hip_stream,
+ * to be timed with events there.  PPP_E_INVALID_ARG for n_blocks < 1,
+ * iters < 1 or a NULL d_out. */
+ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, float *d_out, void *hip_stream);
+
 /* ---- learned window placement ------------------------------------------ */
 
 /* Surrogate F(lambda): 1 -> 64 -> 64 -> 1 tanh MLP with bf16 weights and

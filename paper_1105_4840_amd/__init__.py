@@ -134,6 +134,7 @@ def lib():
             "ppp_eval_forces": ([H, vp, ctypes.c_size_t, vp, ctypes.c_int32, ctypes.c_double, vp, vp, vp], st),
             "ppp_trajectory": ([H, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp], st),
             "ppp_philox": ([ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [ctypes.c_int32, vp, vp, vp, vp], st),
+            "ppp_probe_valu": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp, vp], st),
             "ppp_mlp_forward": ([vp, vp, ctypes.c_int32, vp, vp, vp], st),
             "ppp_mlp_grad": ([vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp], st),
             "ppp_mlp_adam": ([vp, vp, vp, vp, ctypes.c_float, ctypes.c_int32, vp], st),
@@ -154,7 +155,7 @@ def lib():
 EXPORTED = ["ppp_create", "ppp_batch_create", "ppp_workspace_size", "ppp_run", "ppp_begin", "ppp_advance",
             "ppp_finalize", "ppp_steps_done", "ppp_get_result", "ppp_batch_get_result", "ppp_get_timings",
             "ppp_checkpoint", "ppp_restore", "ppp_destroy", "ppp_status_string", "ppp_last_error",
-            "ppp_create_error", "ppp_eval_forces", "ppp_trajectory", "ppp_philox", "ppp_mlp_forward",
+            "ppp_create_error", "ppp_eval_forces", "ppp_trajectory", "ppp_philox", "ppp_probe_valu", "ppp_mlp_forward",
             "ppp_mlp_grad", "ppp_mlp_adam", "ppp_adaptive_workspace_size", "ppp_adaptive_run", "ppp_autotune"]
 
 
@@ -362,6 +363,20 @@ def ppp_philox(seed, c0, c1, c2, c3, n, device="cuda", stream=None):
     st = lib().ppp_philox(int(seed), c0, c1, c2, c3, int(n), _ptr(words), _ptr(z64), _ptr(z32), _stream(stream))
     _check(st, None, "ppp_philox")
     return words.cpu().numpy().view(np.uint32), z64.cpu().numpy(), z32.cpu().numpy()
+
+
+def ppp_probe_valu(n_blocks, iters, b=0.999999, c=1e-7, out=None, device="cuda", stream=None):
+    """Launches the fp32 FMA issue-rate probe (16 * iters flops per thread, n_blocks x 256
+    threads) on `stream` and returns its device output (one fp32 per thread)."""
+    import torch
+    n = int(n_blocks) * 256
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=device)
+    if out.numel() < n or out.dtype != torch.float32:
+        raise ValueError("ppp_probe_valu: out must hold n_blocks * 256 fp32 values")
+    _check(lib().ppp_probe_valu(int(n_blocks), int(iters), float(b), float(c), _ptr(out), _stream(stream)),
+           None, "ppp_probe_valu")
+    return out
 
 
 def ppp_adaptive_run(base: dict, adaptive: dict, stream=None, device="cuda"):

@@ -1,0 +1,30 @@
+// fp32 FMA issue-rate probe.  Eight independent chains per thread hide the FMA
+// latency, so with enough wavefronts per SIMD the loop runs at the VALU issue
+// rate; the chains' sums are written out so that none of them is removed.
+#include "ppp_probe.hpp"
+
+namespace ppp {
+
+__global__ __launch_bounds__(256) void valu_fma_probe(int iters, float b, float c, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float a[kProbeChains];
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) a[k] = (float)((i + k) & 1023) * 1e-6f;
+#pragma unroll 4
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kProbeChains; ++k) a[k] = __builtin_fmaf(a[k], b, c);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kProbeChains; ++k) s += a[k];
+    out[i] = s;
+}
+
+hipError_t launch_valu_probe(int n_blocks, int iters, float b, float c, float *out, hipStream_t stream) {
+    if (n_blocks <= 0 || iters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(valu_fma_probe, dim3(n_blocks), dim3(256), 0, stream, iters, b, c, out);
+    return hipGetLastError();
+}
+
+}  // namespace ppp

@@ -20,6 +20,7 @@
 #include "ppp_internal.hpp"
 #include "ppp_internal_api.hpp"
 #include "ppp_launch.hpp"
+#include "ppp_probe.hpp"
 #include "ppp_shapes.hpp"
 
 using namespace ppp;
@@ -1018,6 +1019,12 @@ ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint
                       double *d_normals, float *d_normals32, void *stream) {
     if (n < 0) return PPP_E_INVALID_ARG;
     hipError_t e = launch_philox(seed, c0, c1, c2, c3, n, d_words, d_normals, d_normals32, (hipStream_t)stream);
+    return e == hipSuccess ? PPP_OK : PPP_E_DEVICE;
+}
+
+ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, float *d_out, void *stream) {
+    if (n_blocks < 1 || iters < 1 || !d_out) return PPP_E_INVALID_ARG;
+    hipError_t e = launch_valu_probe(n_blocks, iters, b, c, d_out, (hipStream_t)stream);
     return e == hipSuccess ? PPP_OK : PPP_E_DEVICE;
 }
 

@@ -564,3 +564,23 @@ def test_every_kernel_shape_resumes_bit_exactly(shape, tmp_path, monkeypatch):
         for key in ("dF_je", "xi_mean", "xi_std", "xi_hist", "n_samples"):
             assert np.array_equal(full[key], part[key], equal_nan=True), (precision, key)
 
+
+
+def test_valu_probe_computes_its_chains():
+    """The issue-rate probe does the arithmetic it is credited with: every thread's
+    output is the sum of its 8 FMA chains, recomputed here in fp64 from the fp32
+    start values (fp32 rounding each step keeps it within 1e-5 relative)."""
+    _say("case valu probe")
+    n_blocks, iters, b, c = 3, 50, 0.999, 1e-3
+    out = ppp.ppp_probe_valu(n_blocks, iters, b=b, c=c).cpu().numpy().astype(np.float64)
+    i = np.arange(n_blocks * 256)
+    want = np.zeros_like(out)
+    b32, c32 = float(np.float32(b)), float(np.float32(c))
+    for k in range(8):
+        a = np.float32(((i + k) & 1023) * np.float32(1e-6)).astype(np.float64)
+        for _ in range(iters):
+            a = a * b32 + c32
+        want += a
+    assert np.allclose(out, want, rtol=1e-5, atol=0)
+    with pytest.raises(ppp.PppError):
+        ppp.ppp_probe_valu(0, 10)
