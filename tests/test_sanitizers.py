@@ -36,7 +36,7 @@ def _kernel_objects():
     build = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(build)
     names = [f"shape_{t}_{g}x{b}.hip.o" for g, b in build.shapes() for t in ("float", "double")]
-    names += ["ppp_sim.hip.o", "ppp_reduce.hip.o", "ppp_mlp.hip.o"]
+    names += [src + ".o" for src in build.SOURCES if src.endswith(".hip")]
     return [os.path.join(PKG, "_build", n) for n in names]
 
 
