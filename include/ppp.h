@@ -226,11 +226,19 @@ typedef struct {
     int64_t replica_steps;
     int32_t sim_launches;
     int32_t variant_lanes, variant_beads_per_lane;  /* kernel shape chosen for the chain */
+    double last_advance_ms;  /* simulation kernel(s) of the latest ppp_advance (or of the whole
+                                relaxation in ppp_run), HIP-event time; NaN for batched handles */
 } ppp_timings;
 
 typedef struct ppp_handle ppp_handle;
 
-/* Validates and copies the problem, chooses the kernel shape (from the table
+/* The parallel pulling protocol of Sec. III(ii) and Fig. 1b: s independent
+ * relaxations, one per window lambda_i, from the shared start state x_o, each
+ * under the restraint of Eq. 3, recording xi for the estimators of Eqs. 9 and
+ * 12-14 and the work distributions of App. C (the run settings and records of
+ * Sec. IV A).
+ *
+ * Validates and copies the problem, chooses the kernel shape (from the table
  * file named by the environment variable PPP_TUNE_TABLE if set, see
  * ppp_autotune, else a built-in heuristic) and the workspace layout.  PPP_E_INVALID_ARG for: s < 2, lambda not strictly
  * monotone or non-finite, k, kT, dt <= 0, n_replicas < 1, sample_every < 1,
@@ -242,7 +250,10 @@ typedef struct ppp_handle ppp_handle;
 ppp_status ppp_create(const ppp_problem *p, ppp_handle **out);
 
 /* Batched form (uneven chains, windows, replicas, steps): all problems run in
- * one persistent, HIP-graph-captured launch.  tune_table_path (optional, may
+ * one persistent, HIP-graph-captured launch.  The paper runs one protocol at a
+ * time; batching several is this library's extension, sound because every
+ * window of every problem is an independent relaxation (Sec. III(ii)), so each
+ * problem gives what its own ppp_run gives, bit for bit.  tune_table_path (optional, may
  * be NULL) is a text file written by ppp_autotune; without it a built-in
  * shape heuristic is used.  Results are read per problem with
  * ppp_batch_get_result. */
@@ -252,20 +263,29 @@ ppp_status ppp_batch_create(const ppp_problem *ps, int32_t n, const char *tune_t
 /* Device bytes the caller must supply to ppp_run (256-byte aligned). */
 ppp_status ppp_workspace_size(const ppp_handle *h, size_t *bytes);
 
-/* Enqueues the whole protocol on hip_stream: initial state, all relaxation
- * steps, reductions, estimators and work distributions.  d_workspace must
+/* Enqueues the whole protocol of Sec. III(ii) (Fig. 1b) on hip_stream: the
+ * shared initial state x_o, all relaxation steps of every window, the
+ * reductions, the estimators of Eqs. 12-14 and the work distributions of
+ * App. C.  d_workspace must
  * stay valid until ppp_get_result returns.  PPP_E_OUT_OF_MEMORY if bytes is
  * below ppp_workspace_size. */
 ppp_status ppp_run(ppp_handle *h, void *d_workspace, size_t bytes, void *hip_stream);
 
-/* Incremental form of ppp_run: begin (initial state), advance by n steps
- * (clamped to the steps left), finalize (reductions and estimators).  */
+/* Incremental form of ppp_run (same protocol, Sec. III(ii)): begin (initial
+ * state), advance by n steps (clamped to the steps left), finalize (reductions,
+ * estimators and App. C on what has been sampled so far; an advance may follow
+ * and a later finalize includes it).  */
 ppp_status ppp_begin(ppp_handle *h, void *d_workspace, size_t bytes, void *hip_stream);
 ppp_status ppp_advance(ppp_handle *h, int64_t n_steps, void *hip_stream);
 ppp_status ppp_finalize(ppp_handle *h, void *hip_stream);
 ppp_status ppp_steps_done(const ppp_handle *h, int64_t *steps);
 
-/* Synchronises the stream of the last run and copies the outputs into the
+/* Results of the run (ppp_result above): the profiles of Eq. 12 (JE over the
+ * step-wise work, factorised over independent windows), Eq. 14 and Eq. 13, the
+ * combined estimate and uncertainty of Sec. IV B and IV D, the window
+ * statistics and histograms of Sec. IV A, the work distributions and variance
+ * formula of App. C, and the overlap diagnostics of Sec. IV B.
+ * Synchronises the stream of the last run and copies the outputs into the
  * caller's host buffers.  Returns PPP_E_NUMERICAL (buffers still filled) when
  * more than 1% of some window's replicas were frozen. */
 ppp_status ppp_get_result(ppp_handle *h, ppp_result *out);
@@ -313,16 +333,6 @@ ppp_status ppp_trajectory(ppp_handle *h, void *d_workspace, size_t bytes, int32_
  * d_normals32: device fp32 [n][4] (fp32 Box-Muller; may be NULL). */
 ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n,
                       uint32_t *d_words, double *d_normals, float *d_normals32, void *hip_stream);
-
-/* Vector-ALU issue-rate probe, not part of the protocol: the fp32 FMA rate
- * the simulation kernels' roofline is read against.  n_blocks workgroups of
- * 256 threads each run 8 independent chains a <- fma(a, b, c) for iters steps
- * (16 iters flops per thread), chain k of thread i starting at
- * ((i + k) mod 1024) 1e-6, and write the sum of the 8 chains to d_out[i]
- * (device fp32 [n_blocks * 256], caller-owned).  Asynchronous on hip_stream,
- * to be timed with events there.  PPP_E_INVALID_ARG for n_blocks < 1,
- * iters < 1 or a NULL d_out. */
-ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, float *d_out, void *hip_stream);
 
 /* ---- learned window placement ------------------------------------------ */
 
@@ -381,7 +391,15 @@ typedef struct {
     int64_t explore_steps;          /* steps per exploration window (0: n_steps / 4) */
     int64_t min_production_steps;   /* relaxation steps every production window gets (see above);
                                        PPP_E_INVALID_ARG if the budget cannot afford them */
+    int32_t placement;              /* where sigma(lambda) comes from: PPP_PLACE_LEARNED (the
+                                       surrogate's curvature, above) or PPP_PLACE_EXPLORED (no
+                                       network: the sample sigma_i of the explored windows,
+                                       interpolated linearly in lambda; same rounds, placement
+                                       rule and budget, to isolate what the surrogate adds) */
 } ppp_adaptive;
+
+#define PPP_PLACE_LEARNED 0
+#define PPP_PLACE_EXPLORED 1
 
 /* base describes the system, the lambda range [lambda[0], lambda[n_windows-1]],
  * replicas and the other run settings; lambda_out (host, capacity

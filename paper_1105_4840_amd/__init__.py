@@ -85,7 +85,8 @@ class ppp_result(ctypes.Structure):
 class ppp_timings(ctypes.Structure):
     _fields_ = [("sim_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double), ("appc_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("replica_steps", ctypes.c_int64), ("sim_launches", ctypes.c_int32),
-                ("variant_lanes", ctypes.c_int32), ("variant_beads_per_lane", ctypes.c_int32)]
+                ("variant_lanes", ctypes.c_int32), ("variant_beads_per_lane", ctypes.c_int32),
+                ("last_advance_ms", ctypes.c_double)]
 
 
 class ppp_adaptive(ctypes.Structure):
@@ -93,7 +94,10 @@ class ppp_adaptive(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("max_windows", ctypes.c_int32),
                 ("target_dl_over_sigma", ctypes.c_double), ("train_iters", ctypes.c_int32),
                 ("lr", ctypes.c_double), ("init_seed", ctypes.c_uint64), ("explore_replicas", ctypes.c_int32),
-                ("explore_steps", ctypes.c_int64), ("min_production_steps", ctypes.c_int64)]
+                ("explore_steps", ctypes.c_int64), ("min_production_steps", ctypes.c_int64),
+                ("placement", ctypes.c_int32)]
+
+PPP_PLACE_LEARNED, PPP_PLACE_EXPLORED = 0, 1
 
 
 _lib = None
@@ -152,7 +156,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ["ppp_create", "ppp_batch_create", "ppp_workspace_size", "ppp_run", "ppp_begin", "ppp_advance",
+EXPORTED = ["ppp_create", "ppp_batch_create", "ppp_workspace_size", "ppp_run", "ppp_begin",
+            "ppp_advance",
             "ppp_finalize", "ppp_steps_done", "ppp_get_result", "ppp_batch_get_result", "ppp_get_timings",
             "ppp_checkpoint", "ppp_restore", "ppp_destroy", "ppp_status_string", "ppp_last_error",
             "ppp_create_error", "ppp_eval_forces", "ppp_trajectory", "ppp_philox", "ppp_probe_valu", "ppp_mlp_forward",
@@ -389,7 +394,8 @@ def ppp_adaptive_run(base: dict, adaptive: dict, stream=None, device="cuda"):
                      float(adaptive.get("target_dl_over_sigma", 1.0)), int(adaptive.get("train_iters", 400)),
                      float(adaptive.get("lr", 3e-3)), int(adaptive.get("init_seed", 1)),
                      int(adaptive.get("explore_replicas", 0)), int(adaptive.get("explore_steps", 0)),
-                     int(adaptive.get("min_production_steps", 0)))
+                     int(adaptive.get("min_production_steps", 0)),
+                     {"learned": PPP_PLACE_LEARNED, "explored": PPP_PLACE_EXPLORED}[adaptive.get("placement", "learned")])
     n = ctypes.c_size_t()
     _check(lib().ppp_adaptive_workspace_size(ctypes.byref(p), ctypes.byref(a), ctypes.byref(n)), None,
            "ppp_adaptive_workspace_size")

@@ -54,6 +54,7 @@ bool valid_adaptive(const ppp_problem *b, const ppp_adaptive *a) {
     if (a->max_windows < a->initial_windows || a->max_windows > 2048) return false;
     if (!(a->target_dl_over_sigma > 0) || a->train_iters < 0 || !(a->lr > 0)) return false;
     if (a->explore_replicas < 0 || a->explore_steps < 0 || a->min_production_steps < 0) return false;
+    if (a->placement != PPP_PLACE_LEARNED && a->placement != PPP_PLACE_EXPLORED) return false;
     return b->n_windows >= 2 && b->lambda && std::isfinite(b->lambda[0]) && std::isfinite(b->lambda[b->n_windows - 1]) &&
            b->lambda[0] != b->lambda[b->n_windows - 1];
 }
@@ -163,7 +164,7 @@ ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void
     const int64_t cost_e = (int64_t)Re * ne;
     int64_t used = 0;
 
-    std::vector<double> xl, xs;        // explored windows: lambda, slope k (lambda - <x>)
+    std::vector<double> xl, xs, xsd;   // explored windows: lambda, slope k (lambda - <x>), sigma_i
     std::vector<double> vl, vF, vw;    // value targets from the first round's JE chain
     std::vector<double> placed;        // latest placement
     std::vector<double> fresh(a->initial_windows);
@@ -195,6 +196,7 @@ ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void
             if (!std::isfinite(ro.mean[i])) continue;
             xl.push_back(fresh[i]);
             xs.push_back(k * (fresh[i] - ro.mean[i]));      // dF/dlambda, Eq. 14 in the small-step limit
+            xsd.push_back(ro.sd[i]);
         }
         if (round == 0) {
             double wmin = 1.0;
@@ -204,6 +206,26 @@ ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void
                 vl.push_back(fresh[i]); vF.push_back(ro.dF_je[i]); vw.push_back(i == 0 ? 1.0 : wmin);
             }
         }
+        const double dl = (hi - lo) / (kGrid - 1);
+        const double s2_free = kT / k;
+        std::vector<double> sig(kGrid);
+        if (a->placement == PPP_PLACE_EXPLORED) {
+            // ---- no network: sigma(lambda) through the explored windows' sample sigma_i ----
+            std::vector<std::pair<double, double>> pts;
+            for (size_t i = 0; i < xl.size(); ++i)
+                if (std::isfinite(xsd[i]) && xsd[i] > 0) pts.push_back({(xl[i] - lo) / dl, xsd[i]});
+            if (pts.size() < 2) break;            // uniform fallback below
+            std::sort(pts.begin(), pts.end());
+            size_t j = 0;
+            for (int i = 0; i < kGrid; ++i) {
+                while (j + 2 < pts.size() && pts[j + 1].first <= i) ++j;
+                const double x0 = pts[j].first, x1 = pts[j + 1].first;
+                const double f = x1 > x0 ? std::min(1.0, std::max(0.0, (i - x0) / (x1 - x0))) : 0.0;
+                const double sd = pts[j].second * (1 - f) + pts[j + 1].second * f;
+                sig[i] = std::sqrt(std::min(std::max(sd * sd, 0.05 * s2_free), 100.0 * s2_free));
+            }
+            trained = true;
+        } else {
         // ---- train the surrogate on all window data ----
         double smax = 0.0, fmax = 1.0;
         for (double v : xs) smax = std::max(smax, std::fabs(v) * std::fabs(half));
@@ -239,17 +261,16 @@ ppp_status ppp_adaptive_run(const ppp_problem *base, const ppp_adaptive *a, void
             hipMemcpyAsync(&loss, mb.loss, 4, hipMemcpyDeviceToHost, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
             return PPP_E_DEVICE;
         bool ok = std::isfinite(loss);
-        std::vector<double> slope(kGrid), sig(kGrid);
+        std::vector<double> slope(kGrid);
         for (int i = 0; i < kGrid; ++i) { slope[i] = (double)gdy[i] * Fs / half; ok = ok && std::isfinite(slope[i]); }
         if (!ok) break;                       // uniform fallback below
         trained = true;
-        const double dl = (hi - lo) / (kGrid - 1);
-        const double s2_free = kT / k;
         for (int i = 0; i < kGrid; ++i) {
             const int a0 = std::max(0, i - 1), a1 = std::min(kGrid - 1, i + 1);
             const double curv = (slope[a1] - slope[a0]) / ((a1 - a0) * dl);          // F''(lambda)
             const double s2 = (k - curv) / (beta * k * k);
             sig[i] = std::sqrt(std::min(std::max(s2, 0.05 * s2_free), 100.0 * s2_free));
+        }
         }
         auto sigma_at = [&](double l) {
             double x = (l - lo) / dl;

@@ -139,11 +139,14 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ float pull_f(int src_lane, float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src_lane << 2, __float_as_int(v)));
 }
+// fp64 values travel as two 32-bit halves; the split and the join are bit
+// casts (no pointer type punning, which would break strict aliasing)
+struct I2 { int lo, hi; };
 __device__ __forceinline__ double pull_f(int src_lane, double v) {
-    int2 w = *reinterpret_cast<int2 *>(&v);
-    w.x = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.x);
-    w.y = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.y);
-    return *reinterpret_cast<double *>(&w);
+    I2 w = __builtin_bit_cast(I2, v);
+    w.lo = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.lo);
+    w.hi = __builtin_amdgcn_ds_bpermute(src_lane << 2, w.hi);
+    return __builtin_bit_cast(double, w);
 }
 __device__ __forceinline__ int pull_i(int src_lane, int v) {
     return __builtin_amdgcn_ds_bpermute(src_lane << 2, v);
@@ -153,10 +156,10 @@ __device__ __forceinline__ float push_f(int dst_lane, float v) {
     return __int_as_float(__builtin_amdgcn_ds_permute(dst_lane << 2, __float_as_int(v)));
 }
 __device__ __forceinline__ double push_f(int dst_lane, double v) {
-    int2 w = *reinterpret_cast<int2 *>(&v);
-    w.x = __builtin_amdgcn_ds_permute(dst_lane << 2, w.x);
-    w.y = __builtin_amdgcn_ds_permute(dst_lane << 2, w.y);
-    return *reinterpret_cast<double *>(&w);
+    I2 w = __builtin_bit_cast(I2, v);
+    w.lo = __builtin_amdgcn_ds_permute(dst_lane << 2, w.lo);
+    w.hi = __builtin_amdgcn_ds_permute(dst_lane << 2, w.hi);
+    return __builtin_bit_cast(double, w);
 }
 
 }  // namespace ppp

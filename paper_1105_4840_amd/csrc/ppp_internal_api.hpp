@@ -2,6 +2,8 @@
 #pragma once
 #include <stddef.h>
 
+#include <string>
+
 #include "ppp.h"
 
 namespace ppp {

@@ -20,6 +20,7 @@
 #include "ppp_internal.hpp"
 #include "ppp_internal_api.hpp"
 #include "ppp_launch.hpp"
+#include "ppp_probe.h"
 #include "ppp_probe.hpp"
 #include "ppp_shapes.hpp"
 
@@ -50,6 +51,7 @@ struct VariantGroup {
 
 struct ppp_handle {
     std::vector<ProblemHost> probs;
+    std::vector<DevProblem> dev;     // the problems' device records, built with the layout
     std::vector<WorkItem> items;
     std::vector<VariantGroup> groups;
     bool batch = false;
@@ -62,7 +64,8 @@ struct ppp_handle {
     bool begun = false, finalized = false, ran = false, restored = false;
     int64_t steps_done = 0;
     std::string err;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[8] = {};       // 0-4: begin, sim start, reduce, App. C, end; 5-6: last advance
+    bool advanced = false;       // ev[5], ev[6] hold an advance
     bool events_ok = false;
     int sim_launches = 0;
     // batch graph
@@ -131,6 +134,9 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
     if (p->n_steps < 1 || p->n_steps > 0xffffffffLL) { msg = "n_steps must be in [1, 2^32)"; return PPP_E_INVALID_ARG; }
     if (p->n_equil < 0 || p->n_equil >= p->n_steps) { msg = "need 0 <= n_equil < n_steps"; return PPP_E_INVALID_ARG; }
     if (p->n_pull < 0) { msg = "n_pull must be >= 0"; return PPP_E_INVALID_ARG; }
+    // samples taken while the centre still moves would be charged the work and the
+    // window mean of the fixed lambda_i (Eqs. 9, 14): the pull must end before sampling
+    if (p->n_pull > p->n_equil) { msg = "need n_pull <= n_equil (no samples while the centre moves)"; return PPP_E_INVALID_ARG; }
     if (p->xi_nbins < 1) { msg = "xi_nbins must be >= 1"; return PPP_E_INVALID_ARG; }
     if (!finite_pos(p->xi_bin) || !std::isfinite(p->xi_min)) { msg = "xi_bin must be > 0, xi_min finite"; return PPP_E_INVALID_ARG; }
     if (p->w_half_bins < 0 || p->w_half_bins > 50000000) { msg = "w_half_bins out of range"; return PPP_E_INVALID_ARG; }
@@ -378,6 +384,8 @@ void finish_layout(ppp_handle *h) {
         h->max_m = std::max(h->max_m, ph.dev.w_half_bins);
     }
     h->ws_bytes = at;
+    h->dev.clear();
+    for (auto &ph : h->probs) h->dev.push_back(ph.dev);
 }
 
 ppp_status check_ws(ppp_handle *h, void *ws, size_t bytes) {
@@ -391,9 +399,7 @@ const DevProblem *d_probs(ppp_handle *h) { return reinterpret_cast<const DevProb
 const WorkItem *d_items(ppp_handle *h) { return reinterpret_cast<const WorkItem *>(h->ws + h->off_items); }
 
 ppp_status upload(ppp_handle *h, hipStream_t st) {
-    std::vector<DevProblem> dp;
-    for (auto &ph : h->probs) dp.push_back(ph.dev);
-    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_probs, dp.data(), dp.size() * sizeof(DevProblem), hipMemcpyHostToDevice, st));
+    HIPCHK(h, hipMemcpyAsync(h->ws + h->off_probs, h->dev.data(), h->dev.size() * sizeof(DevProblem), hipMemcpyHostToDevice, st));
     if (!h->items.empty())
         HIPCHK(h, hipMemcpyAsync(h->ws + h->off_items, h->items.data(), h->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st));
     for (auto &ph : h->probs) {
@@ -411,6 +417,18 @@ ppp_status ensure_events(ppp_handle *h) {
     h->events_ok = true;
     return PPP_OK;
 }
+
+// Records event i on st when the handle has its events (a run without them, the
+// allocation-free entry point's on a fresh handle, takes no timings).
+ppp_status mark(ppp_handle *h, int i, hipStream_t st) {
+    if (h->events_ok) HIPCHK(h, hipEventRecord(h->ev[i], st));
+    return PPP_OK;
+}
+#define MARK(h, i, st)                                   \
+    do {                                                 \
+        ppp_status m_ = mark((h), (i), (st));            \
+        if (m_ != PPP_OK) return m_;                     \
+    } while (0)
 
 ppp_status launch_items(ppp_handle *h, const ProblemHost &ph, int64_t b, int64_t e, hipStream_t st, double *traj,
                         int64_t traj_rep, int first, int count) {
@@ -528,19 +546,20 @@ ppp_status copy_result(ppp_handle *h, const ProblemHost &ph, ppp_result *out) {
     return PPP_OK;
 }
 
-ppp_status do_begin(ppp_handle *h, void *ws, size_t bytes, hipStream_t st) {
+ppp_status do_begin(ppp_handle *h, void *ws, size_t bytes, hipStream_t st, bool timing = true) {
     ppp_status s = check_ws(h, ws, bytes);
     if (s != PPP_OK) return s;
-    if ((s = ensure_events(h)) != PPP_OK) return s;
+    if (timing && (s = ensure_events(h)) != PPP_OK) return s;
     h->ws = static_cast<char *>(ws);
     h->stream = st;
     if ((s = upload(h, st)) != PPP_OK) return s;
-    HIPCHK(h, hipEventRecord(h->ev[0], st));
+    MARK(h, 0, st);
     HIPCHK(h, launch_init(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_k, h->max_m,
                           reinterpret_cast<int *>(h->ws + h->off_tickets), 64, st));
     // the first advance starts at step 0, where the kernel builds the initial state
-    HIPCHK(h, hipEventRecord(h->ev[1], st));
+    MARK(h, 1, st);
     h->begun = true; h->finalized = false; h->restored = false; h->steps_done = 0; h->sim_launches = 0;
+    h->advanced = false;
     return PPP_OK;
 }
 
@@ -551,12 +570,15 @@ ppp_status do_advance(ppp_handle *h, int64_t n, hipStream_t st) {
     for (auto &ph : h->probs) maxsteps = std::max(maxsteps, total_steps(ph));
     const int64_t e = std::min(maxsteps, h->steps_done + n);
     if (e <= h->steps_done) return PPP_OK;
+    MARK(h, 5, st);
     for (auto &ph : h->probs) {
         const int64_t pe = std::min(e, total_steps(ph));
         if (pe <= h->steps_done) continue;
         ppp_status s = launch_items(h, ph, h->steps_done, pe, st, nullptr, -1, ph.first_item, ph.n_items);
         if (s != PPP_OK) return s;
     }
+    MARK(h, 6, st);
+    h->advanced = true;
     h->steps_done = e;
     h->sim_launches++;
     h->stream = st;
@@ -581,12 +603,12 @@ ppp_status do_finalize(ppp_handle *h, hipStream_t st) {
             }
         }
     }
-    HIPCHK(h, hipEventRecord(h->ev[2], st));
+    MARK(h, 2, st);
     HIPCHK(h, launch_reduce(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_blocks, st));
     HIPCHK(h, launch_estimators(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, st));
-    HIPCHK(h, hipEventRecord(h->ev[3], st));
+    MARK(h, 3, st);
     HIPCHK(h, launch_appc(d_probs(h), (int)h->probs.size(), h->ws, h->max_windows, h->max_m, st));
-    HIPCHK(h, hipEventRecord(h->ev[4], st));
+    MARK(h, 4, st);
     h->finalized = true;
     h->ran = true;
     h->stream = st;
@@ -818,6 +840,7 @@ ppp_status ppp_get_timings(const ppp_handle *hc, ppp_timings *out) {
         out->appc_ms = ev_ms(h->ev[3], h->ev[4]);
     }
     out->total_ms = ev_ms(h->ev[0], h->ev[4]);
+    out->last_advance_ms = h->advanced && !h->batch ? ev_ms(h->ev[5], h->ev[6]) : NAN;
     int64_t rs = 0;
     for (auto &ph : h->probs)
         rs += ph.dev.sequential ? (int64_t)ph.dev.n_replicas * std::min(total_steps(ph), h->steps_done)

@@ -15,7 +15,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "ppp.h")).read()
+    """Every function declared in include/*.h."""
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     return sorted(set(re.findall(r"^(?:ppp_status|const char \*)\s*(ppp_\w+)\(", text, flags=re.M)))
 
 
@@ -64,6 +66,8 @@ def _status(prob):
     lambda p: p.update(n_beads=100000),
     lambda p: p.update(mass=0.0),
     lambda p: p.update(rc_mode=3),
+    # the centre would still move while samples are taken (n_equil = 10 here)
+    lambda p: p.update(n_pull=11),
 ])
 def test_invalid_chain_problems_rejected(mutate):
     p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
@@ -81,6 +85,15 @@ def test_invalid_1d_problems_rejected():
     p = ppp_inputs.config_1d(n_replicas=4, n_steps=100)
     p["pot_kind"] = 9
     assert _status(p) == ppp.PPP_E_INVALID_ARG
+
+
+def test_pull_ending_at_the_first_sample_is_accepted():
+    p = ppp_inputs.config_chain10(n_replicas=8, n_steps=100)
+    p["n_pull"] = p["n_equil"]
+    assert _status(p) == 0
+    p["n_pull"] = p["n_equil"] + 1
+    assert _status(p) == ppp.PPP_E_INVALID_ARG
+    assert "n_pull" in ppp.lib().ppp_create_error().decode()
 
 
 def test_valid_problems_and_workspace_size():

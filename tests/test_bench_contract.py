@@ -50,3 +50,23 @@ def test_oracle_baseline_reports_its_sample_and_host():
     assert out["value"] > 0 and out["cores"] >= 1
     assert "windows" in out["sample"] and "replicas" in out["sample"]
     assert out["host"]["logical_cpus"] >= 1
+
+
+def test_chunked_bench_refuses_more_steps_than_the_workload_has():
+    """A bench step of the 256-bead workload advances it by --chunk steps; asking
+    for more steps than the run has is refused before any device work."""
+    import argparse
+    args = argparse.Namespace(warmup=5, steps=20, chunk=20000, workload="chain256")
+    with pytest.raises(SystemExit) as e:
+        bench.chunked_bench(args, ppp_inputs.config_chain256(), "", None)
+    assert "exceeds" in str(e.value)
+
+
+def test_oracle_baseline_keeps_a_pull_gentle_when_it_shortens_the_run():
+    """Cut to fewer steps, a pulled run keeps the pull and the equilibration over the
+    first two thirds of them and counts the steps its replicas actually ran."""
+    prob = ppp_inputs.config_chain_small(4, n_replicas=4, n_steps=200000, n_windows=3, precision="fp64")
+    prob["n_pull"] = 10000
+    prob["n_equil"] = 20000
+    out = bench.cpu_baseline(prob, 0.05)
+    assert "pull and equilibration over the first" in out["sample"] and "0 replicas frozen" in out["sample"]

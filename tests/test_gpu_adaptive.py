@@ -42,7 +42,7 @@ def test_adaptive_double_well_meets_overlap_target_and_quadrature():
     exact = F - F[0]
     z = (res["dF_je"][-1] - exact[-1]) / res["dF_je_se"][-1]
     print(f"  dF_je end {res['dF_je'][-1]:.4f} exact {exact[-1]:.4f} z {z:.2f}", flush=True)
-    assert abs(z) < 3.5
+    assert abs(z) < 3.0
 
 
 def test_learned_placement_beats_uniform_windows_at_half_the_budget():
@@ -71,4 +71,45 @@ def test_learned_placement_beats_uniform_windows_at_half_the_budget():
     assert used <= budget // 2
     assert err_u > 1.0                                  # the uniform protocol fails here
     assert err_l < 0.25 * err_u
-    assert err_l < 3.5 * res["dF_je_se"][-1] + 0.05
+    assert err_l < 3.0 * res["dF_je_se"][-1] + 0.05
+
+
+def _stiff_double_well():
+    base = ppp_inputs.config_1d(n_replicas=256, n_steps=20000, precision="fp64", seed=5)
+    base.update({"k": 800.0, "n_blocks": 16, "w_half_bins": 0})
+    return base
+
+
+def test_surrogate_against_equal_budget_baselines():
+    """What the network adds beyond more windows: at the same half budget as the
+    learned placement, (a) uniform windows at the count the learned placement
+    chose (the budget all in production) and (b) the same exploration rounds and
+    placement rule with sigma(lambda) interpolated from the explored windows'
+    sample sigma_i instead of the surrogate's curvature.  On this double well
+    the restrained sigma hardly varies with lambda (kT/(k + U'') with k = 800
+    and |U''| <= 40), so all three should land within their errors of the exact
+    dF(1.5) = 0; the errors and their standard errors are printed, which is the
+    comparison, and each is checked against 3 SE."""
+    print("case surrogate vs equal-budget baselines 1d k=800", flush=True)
+    base = _stiff_double_well()
+    budget = 21 * 256 * 20000 // 2
+    ad = {"budget_replica_steps": budget, "initial_windows": 11, "max_rounds": 5, "max_windows": 192,
+          "target_dl_over_sigma": 1.0, "train_iters": 600, "lr": 3e-3, "init_seed": 3,
+          "explore_replicas": 32, "explore_steps": 2000, "min_production_steps": 1000}
+    learned, lam, used = ppp.ppp_adaptive_run(dict(base, n_steps=4000), ad)
+    explored, lam_e, used_e = ppp.ppp_adaptive_run(dict(base, n_steps=4000), dict(ad, placement="explored"))
+    W = len(lam)
+    steps = budget // (W * base["n_replicas"])
+    uni = dict(base, n_steps=steps, n_equil=steps // 10, **{"lambda": list(np.linspace(-1.5, 1.5, W))})
+    uniform, _ = ppp.run(uni)
+    rows = (("learned", learned, used, W), ("explored sigma, no network", explored, used_e, len(lam_e)),
+            (f"uniform x{W}", uniform, W * base["n_replicas"] * steps, W))
+    for name, r, u, w in rows:
+        print(f"  {name}: {w} windows, {u:.3g} replica-steps, max dl/sigma "
+              f"{np.nanmax(r['dlambda_over_sigma']):.2f}, dF_je(1.5) {r['dF_je'][-1]:+.4f} "
+              f"+- {r['dF_je_se'][-1]:.4f}", flush=True)
+        assert u <= budget
+        assert abs(r["dF_je"][-1]) < 3.0 * r["dF_je_se"][-1] + 0.01, name
+    d = abs(learned["dF_je"][-1]) - abs(explored["dF_je"][-1])
+    print(f"  |err| learned - |err| explored: {d:+.4f} (combined se "
+          f"{np.hypot(learned['dF_je_se'][-1], explored['dF_je_se'][-1]):.4f})", flush=True)

@@ -187,7 +187,7 @@ def _compare_runs(prob, res, ref, prof_tol=1e-9):
 RUN_CASES = [
     ("1d", dict(n_replicas=300, n_steps=3000, n_windows=21), None),
     ("1d-em", dict(n_replicas=70, n_steps=2000, n_windows=6), {"integrator_1d": 1}),
-    ("1d-pull", dict(n_replicas=40, n_steps=2000, n_windows=6), {"n_pull": 500}),
+    ("1d-pull", dict(n_replicas=40, n_steps=2000, n_windows=6), {"n_pull": 500, "n_equil": 500}),
     ("chain10", 10, dict(n_replicas=70, n_steps=600, n_windows=5)),
     ("chain32", 32, dict(n_replicas=70, n_steps=400, n_windows=4)),
     ("chain37", 37, dict(n_replicas=20, n_steps=300, n_windows=4)),
@@ -342,6 +342,7 @@ def test_sequential_run_parity_fp64(case):
         prob = ppp_inputs.config_1d(precision="fp64", **kw)
         if name.endswith("pull"):
             prob["n_pull"] = 200
+            prob["n_equil"] = 200
     else:
         prob = ppp_inputs.config_chain_small(n_beads, precision="fp64", **kw)
         prob["w_bin"] = 0.05
@@ -459,15 +460,15 @@ def test_fp32_chain_statistics_match_oracle():
     ref = estimators.estimate(p64, xi, kept, with_appc=False)
     for key in ("dF_je", "dF_fluct", "dF_gauss"):
         se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
-        assert abs(res[key][-1] - ref[key][-1]) < 3.5 * se, (key, res[key][-1], ref[key][-1], se)
+        assert abs(res[key][-1] - ref[key][-1]) < 3.0 * se, (key, res[key][-1], ref[key][-1], se)
 
 
 FP32_SLICES = [
     # (name, problem, estimators asserted): the workloads' own step counts, fewer replicas
     ("chain10", lambda: ppp_inputs.config_chain10(n_replicas=64), ("dF_je", "dF_fluct", "dF_gauss", "dF_com")),
-    # uniform windows 5.7 sigma apart: JE rests on rare samples there, so only its
-    # error is stated; the moment-based estimators are asserted
-    ("chain32", lambda: ppp_inputs.config_chain32(n_replicas=16), ("dF_fluct", "dF_gauss")),
+    # uniform windows up to 5.7 sigma apart: JE rests on rare samples there and its
+    # jackknife error is large, but it is still asserted at 3 combined SE
+    ("chain32", lambda: ppp_inputs.config_chain32(n_replicas=16), ("dF_je", "dF_fluct", "dF_gauss", "dF_com")),
 ]
 
 
@@ -475,7 +476,7 @@ FP32_SLICES = [
 def test_fp32_error_vs_fp64_oracle(case):
     """Precision split: fp32 forces and integration with fp64 work accumulation
     against the all-fp64 oracle on the same inputs and noise streams; the error
-    of every dF at the last window is printed and checked against 3.5 combined
+    of every dF at the last window is printed and checked against 3 combined
     jackknife standard errors."""
     name, make, asserted = case
     _say(f"case fp32 vs fp64 oracle {name}")
@@ -491,8 +492,104 @@ def test_fp32_error_vs_fp64_oracle(case):
         se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
         line.append(f"{key} gpu {res[key][-1]:.4f} oracle {ref[key][-1]:.4f} err {err:+.4f} (combined se {se:.4f})")
         if key in asserted:
-            assert abs(err) < 3.5 * se, line[-1]
+            assert abs(err) < 3.0 * se, line[-1]
     _say(f"fp32 error {name}: " + "; ".join(line))
+
+
+def _window_mean_z(res, xi, kept, R):
+    """z of the fp32 window means against the fp64 oracle's: the oracle's replicas
+    give the standard error of one run's window mean (replica means are
+    independent); the two runs have the same spread, so the difference has sqrt(2)
+    times that error."""
+    s = len(res["xi_mean"])
+    z = np.zeros(s)
+    for w in range(s):
+        rows = xi[w * R:(w + 1) * R]
+        n = kept[w * R:(w + 1) * R]
+        m = np.array([rows[r, :n[r]].mean() for r in range(R) if n[r] > 0])
+        se = np.sqrt(2.0) * m.std(ddof=1) / np.sqrt(len(m))
+        z[w] = (res["xi_mean"][w] - rows[~np.isnan(rows)].mean()) / se
+    return z
+
+
+@pytest.mark.slow
+def test_fp32_error_vs_fp64_oracle_chain256():
+    """Precision split on the 256-bead workload: fp32 forces and integration with
+    fp64 work against the all-fp64 oracle on every one of its 41 windows, 16
+    replicas each, 3000 steps with the pull from the helix over the first 2000
+    (the full run pulls over 10000 of its 200000; a faster pull than this
+    compresses the chain into Lennard-Jones overlaps in the low windows).  The
+    windows do not relax in 1000 steps, which both sides share: the comparison
+    is of the same non-equilibrium protocol.  Eq. 14 and Eq. 13 at the last
+    window within 3 combined jackknife SE; the 41 window means through their z
+    values (mean z^2 near 1; the largest of 41 below 4.5); the JE error printed,
+    not asserted: these windows lie about 20 sigma apart, where JE rests on the
+    rarest samples (Sec. IV B)."""
+    _say("case fp32 vs fp64 oracle chain256 (41 windows x 16 replicas x 3000 steps)")
+    prob = ppp_inputs.config_chain256(n_replicas=16, n_steps=3000)
+    prob.update({"n_pull": 2000, "n_equil": 2000, "n_blocks": 8})
+    res, _ = ppp.run(prob)
+    p64 = dict(prob, precision="fp64")
+    xi, kept, _ = oracle.run(p64)
+    ref = estimators.estimate(p64, xi, kept, with_appc=False)
+    assert int(res["n_blown_up"].sum()) == 0 and int(ref["n_blown_up"].sum()) == 0
+    line = []
+    for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com"):
+        err = res[key][-1] - ref[key][-1]
+        se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
+        line.append(f"{key} gpu {res[key][-1]:.3f} oracle {ref[key][-1]:.3f} err {err:+.3f} (combined se {se:.3f})")
+        if key in ("dF_fluct", "dF_gauss"):
+            assert abs(err) < 3.0 * se, line[-1]
+    z = _window_mean_z(res, xi, kept, 16)
+    _say("fp32 error chain256: " + "; ".join(line))
+    _say(f"  window means: mean z^2 {np.mean(z ** 2):.2f}, max |z| {np.max(np.abs(z)):.2f}; "
+         f"max dlambda/sigma {np.max(res['dlambda_over_sigma']):.1f}")
+    assert np.mean(z ** 2) < 2.0 and np.max(np.abs(z)) < 4.5
+
+
+# four chains of the uneven batch, one per kernel shape of its length class
+C2_SLICE = (5, 9, 61, 11)
+
+
+@pytest.mark.slow
+def test_fp32_batch_error_vs_fp64_oracle():
+    """Precision split on the uneven batch: four of its chains (8, 23, 52 and 128
+    beads, one per kernel shape the batch uses for them) with their own windows,
+    32 replicas each and a shortened schedule (3000 steps, the pull and the
+    equilibration over the first 1000), run in fp32 as one batched graph, against
+    the fp64 oracle on each problem.  Eq. 14 and Eq. 13 within 3 combined SE;
+    JE asserted where adjacent windows lie within 3 sigma, printed elsewhere."""
+    inst = ppp_inputs.batched_instances()
+    probs = []
+    for i in C2_SLICE:
+        p = dict(inst[i])
+        p.update({"n_replicas": 32, "n_steps": 3000, "n_equil": 1000, "n_pull": 1000, "n_blocks": 16,
+                  "w_half_bins": 0})
+        probs.append(p)
+    _say("case fp32 batch vs fp64 oracle, chains " + ", ".join(f"N={p['n_beads']}" for p in probs))
+    h = ppp.ppp_batch_create(probs)
+    try:
+        ws = ppp.workspace(h)
+        ppp.ppp_run(h, ws)
+        torch.cuda.synchronize()
+        got = [ppp.ppp_batch_get_result(h, p, i) for i, p in enumerate(probs)]
+    finally:
+        ppp.ppp_destroy(h)
+    for p, res in zip(probs, got):
+        p64 = dict(p, precision="fp64")
+        xi, kept, _ = oracle.run(p64)
+        ref = estimators.estimate(p64, xi, kept, with_appc=False)
+        assert int(res["n_blown_up"].sum()) == 0 and int(ref["n_blown_up"].sum()) == 0
+        dls = float(np.max(ref["dlambda_over_sigma"]))
+        asserted = ("dF_fluct", "dF_gauss") + (("dF_je", "dF_com") if dls <= 3.0 else ())
+        line = []
+        for key in ("dF_je", "dF_fluct", "dF_gauss", "dF_com"):
+            err = res[key][-1] - ref[key][-1]
+            se = np.sqrt(res[key + "_se"][-1] ** 2 + ref[key + "_se"][-1] ** 2)
+            line.append(f"{key} err {err:+.3f} (se {se:.3f})")
+            if key in asserted:
+                assert abs(err) < 3.0 * se, (p["name"], line[-1])
+        _say(f"fp32 error batch {p['name']} N={p['n_beads']} max dl/sigma {dls:.1f}: " + "; ".join(line))
 
 
 def _shapes():

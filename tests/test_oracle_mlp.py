@@ -69,3 +69,34 @@ def test_adam_reduces_loss_and_fits_a_line():
         L, g = mlp.loss_and_grad(th, t, yv, wv, yv, ws, False)
         th, m, v = mlp.adam(th, g, m, v, 3e-3, k)
     assert L < 1e-3 * L0
+
+
+def test_adam_closed_form_steps():
+    """Adam's update written out by hand (Kingma & Ba, beta1 = 0.9, beta2 = 0.999,
+    eps = 1e-8 outside the square root, bias correction by 1 - beta^t):
+      * step 1: m^ = g and v^ = g^2 exactly, so every parameter moves by
+        -lr g / (|g| + eps): lr against the sign of g for |g| >> eps, and
+        lr/11 for |g| = eps/10 (eps inside the root would give lr 1e-5 there;
+        no bias correction would give lr sqrt(1000)/10 = 3.16 lr);
+      * a constant gradient keeps m^ = g and v^ = g^2 at every step, so every
+        step moves by the same -lr g / (|g| + eps) (a wrong power of beta in
+        the correction breaks this from step 2 on);
+      * g = 2 then g = -1: m_2 = 0.9*0.1*2 - 0.1 = 0.08, m^_2 = 0.08/0.19;
+        v_2 = 0.999*0.001*4 + 0.001 = 0.004996, v^_2 = 0.004996/0.001999."""
+    lr = 1e-3
+    g = np.array([2.0, -0.5, 1e-9, -3e4])
+    th1, m, v = mlp.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), lr, 1)
+    assert np.allclose(th1[[0, 1, 3]], [-lr, lr, lr], rtol=1e-7, atol=0)
+    assert abs(th1[2] - (-lr / 11.0)) < 1e-12 * lr
+    assert np.allclose(m, 0.1 * g, rtol=1e-15) and np.allclose(v, 0.001 * g * g, rtol=1e-15)
+    th, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    gc = np.array([0.7, -2.0, 5.0, -1e-3])
+    for step in range(1, 8):
+        prev = th.copy()
+        th, m, v = mlp.adam(th, gc, m, v, lr, step)
+        assert np.allclose(th - prev, -lr * gc / (np.abs(gc) + 1e-8), rtol=1e-9, atol=0), step
+    th, m, v = mlp.adam(np.zeros(1), np.array([2.0]), np.zeros(1), np.zeros(1), lr, 1)
+    th, m, v = mlp.adam(th, np.array([-1.0]), m, v, lr, 2)
+    mh, vh = 0.08 / 0.19, 0.004996 / 0.001999
+    assert abs(m[0] - 0.08) < 1e-15 and abs(v[0] - 0.004996) < 1e-15
+    assert abs(th[0] - (-lr * 2.0 / (2.0 + 1e-8) - lr * mh / (np.sqrt(vh) + 1e-8))) < 1e-15

@@ -175,6 +175,101 @@ def test_em_stationary_variance_closed_form():
     assert v - 1.0 / K > 8 * se               # and it is visibly biased
 
 
+def test_baoab_harmonic_position_variance_is_exact():
+    """BAOAB samples the exact position variance kT/K of a harmonic oscillator at
+    any stable step (a 2x2 Lyapunov fixed point; the momentum variance is
+    kT (1 - K dt^2/4) instead).  A two-bead chain with no bond, the projection
+    reaction coordinate (xi = z_1 - z_0) and the restraint as the only force is
+    that oscillator in z with K = k.  At k dt^2/4 = 0.45 the other splittings are
+    far off: ABOBA, for one, gives kT/(K (1 - K dt^2/4)) = 1.82 kT/K."""
+    k, dt, R = 20.0, 0.3, 256
+    p = ppp_inputs.config_chain_small(2, n_replicas=R, n_steps=21000, n_windows=2, seed=9)
+    p.update({"k_bond": 0.0, "k_angle": 0.0, "lj_eps": 0.0, "rc_mode": 1, "k": k, "dt": dt,
+              "lambda": [0.0, 0.5], "init_coords": [0.0, 0.0, 0.0, 1.0, 0.0, 0.25],
+              "n_equil": 1000, "sample_every": 20})
+    xi, kept, _ = oracle.run(p)
+    assert np.all(kept == xi.shape[1])
+    for w, lam in enumerate(p["lambda"]):
+        x = xi[w * R:(w + 1) * R]
+        v = x.var(axis=1, ddof=1)
+        se_v = v.std(ddof=1) / np.sqrt(R)
+        assert abs(v.mean() - p["kT"] / k) < 3 * se_v, (w, v.mean(), se_v)
+        mu = x.mean(axis=1)
+        assert abs(mu.mean() - lam) < 3 * mu.std(ddof=1) / np.sqrt(R), (w, mu.mean())
+    assert 8 * se_v < p["kT"] / k * 0.82            # the ABOBA value would fail by far
+
+
+def test_linear_pull_schedule_hand_case_1d():
+    """Reading R15: the restraint centre moves linearly from xi(x_o) to lambda_i over
+    the first n_pull steps and then stays; the force on the state after m steps
+    uses the centre c_m = xi(x_o) + (lambda_i - xi(x_o)) m / n_pull (m < n_pull).
+    With the noise switched off (kT = 1e-200) the overdamped harmonic particle
+    follows x_{m+1} = x_m + dt (-kappa x_m - k (x_m - c_m)) with the centres
+    listed by hand; after the pull it relaxes geometrically to k lambda/(kappa+k)."""
+    kappa, k, dt, lam, x0 = 4.0, 20.0, 1e-3, 2.0, -1.0
+    p = ppp_inputs.config_harmonic_1d(kappa=kappa, k=k, n_replicas=1, n_steps=60)
+    p.update({"lambda": [0.5, lam], "init_coords": [x0], "kT": 1e-200, "n_pull": 8, "n_equil": 8, "dt": dt})
+    tr = oracle.trajectory(p, 1, 0, 60)[:, 0]
+    centres = [-1.0, -0.625, -0.25, 0.125, 0.5, 0.875, 1.25, 1.625] + [2.0] * 52
+    x = [x0]
+    for c in centres:
+        x.append(x[-1] + dt * (-kappa * x[-1] - k * (x[-1] - c)))
+    assert np.max(np.abs(tr - np.array(x))) < 1e-14
+    fixed = k * lam / (kappa + k)
+    geo = (x[8] - fixed) * (1 - dt * (kappa + k)) ** np.arange(53) + fixed
+    assert np.max(np.abs(tr[8:] - geo)) < 1e-13
+    # no pull: the centre sits at lambda_i from the first step
+    q = dict(p, n_pull=0)
+    tr0 = oracle.trajectory(q, 1, 0, 5)[:, 0]
+    assert abs(tr0[1] - (x0 + dt * (-kappa * x0 - k * (x0 - lam)))) < 1e-15
+
+
+def test_linear_pull_schedule_hand_case_chain():
+    """The same schedule for a chain starts from the start state's reaction
+    coordinate: two beads, no bond, xi = z_1 - z_0 = 1.5 at the start, the
+    restraint the only force; with the noise off BAOAB moves z alone:
+    v += dt/2 F; z += dt/2 v; v = e^{-gamma dt} v; z += dt/2 v; F = -k (z - c_m);
+    v += dt/2 F, with c_m = 1.5 + (4 - 1.5) m/10 for m < 10, then 4."""
+    k, dt, g = 20.0, 0.05, 1.0
+    p = ppp_inputs.config_chain_small(2, n_replicas=1, n_steps=40, n_windows=2)
+    p.update({"k_bond": 0.0, "k_angle": 0.0, "lj_eps": 0.0, "rc_mode": 1, "k": k, "dt": dt, "gamma": g,
+              "kT": 1e-200, "lambda": [1.0, 4.0], "init_coords": [0.0, 0.0, 0.0, 0.3, -0.2, 1.5],
+              "n_pull": 10, "n_equil": 10})
+    tr = oracle.trajectory(p, 1, 0, 40)
+    cm = [1.5, 1.75, 2.0, 2.25, 2.5, 2.75, 3.0, 3.25, 3.5, 3.75] + [4.0] * 31
+    z, v = 1.5, 0.0
+    f = -k * (z - cm[0])
+    zs = [z]
+    for m in range(1, 41):
+        v += 0.5 * dt * f
+        z += 0.5 * dt * v
+        v *= np.exp(-g * dt)
+        z += 0.5 * dt * v
+        f = -k * (z - cm[m])
+        v += 0.5 * dt * f
+        zs.append(z)
+    assert np.max(np.abs(tr[:, 5] - np.array(zs))) < 1e-13
+    assert np.max(np.abs(tr[:, 3:5] - [0.3, -0.2])) < 1e-90       # x, y feel no force
+    assert np.all(tr[:, :3] == 0.0)                                 # bead 0 is fixed
+
+
+def test_pulled_harmonic_je_matches_closed_form():
+    """A run with the pull (n_pull > 0, sampling after it) from a start state far
+    outside the windows still gives the equilibrium profile: JE and Eq. 13
+    against the closed form of the restrained harmonic oscillator within 3 SE."""
+    p = ppp_inputs.config_harmonic_1d(n_replicas=256, n_steps=8000)
+    p.update({"init_coords": [-3.0], "n_pull": 1500, "n_equil": 2000})
+    xi, kept, _ = oracle.run(p)
+    r = estimators.estimate(p, xi, kept, with_appc=False)
+    Fc, mu, var = quadrature.harmonic_closed_form(p["pot_kappa"], p["k"], p["kT"], p["lambda"])
+    fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
+    for est, ref in (("dF_je", Fc - Fc[0]), ("dF_gauss", g)):
+        z = (r[est][-1] - ref[-1]) / r[est + "_se"][-1]
+        assert abs(z) < 3.0, (est, r[est][-1], ref[-1], r[est + "_se"][-1])
+    zm = (r["xi_mean"] - mu) / (r["xi_std"] / np.sqrt(r["n_samples"] / 20.0))
+    assert np.max(np.abs(zm)) < 4.0
+
+
 def test_trajectory_matches_run_samples():
     """The parity hook replays the same replica as the full run."""
     prob = ppp_inputs.config_chain_small(6, n_replicas=4, n_steps=60)
@@ -257,7 +352,7 @@ def test_oracle_je_matches_harmonic_closed_form():
     fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
     for est, ref in (("dF_je", exact), ("dF_gauss", g), ("dF_fluct", fl)):
         z = (r[est][-1] - ref[-1]) / r[est + "_se"][-1]
-        assert abs(z) < 3.5, (est, r[est][-1], ref[-1], r[est + "_se"][-1])
+        assert abs(z) < 3.0, (est, r[est][-1], ref[-1], r[est + "_se"][-1])
     assert np.allclose(r["gamma2"], p["k"] / (p["k"] + p["pot_kappa"]), rtol=0.05)
 
 
@@ -271,7 +366,7 @@ def test_oracle_je_matches_double_well_quadrature():
     assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 4.0
     # dF_fluct is biased by construction (the exact moments put it about -2 kT off at the end)
     fl, g = quadrature.estimator_expectations(p["lambda"], mu, var, p["k"], p["kT"])
-    assert abs((r["dF_fluct"][-1] - fl[-1]) / r["dF_fluct_se"][-1]) < 3.5
+    assert abs((r["dF_fluct"][-1] - fl[-1]) / r["dF_fluct_se"][-1]) < 3.0
     assert fl[-1] < -1.9
 
 
@@ -289,7 +384,9 @@ def test_oracle_chain_je_matches_quadrature(n_beads):
         F, mu, var = quadrature.chain3(p["lambda"], p["k"], p["kT"], p["k_bond"], p["r0"], p["k_angle"])
     exact = F - F[0]
     z = (r["dF_je"] - exact)[1:] / r["dF_je_se"][1:]
-    assert np.max(np.abs(z)) < 3.5, z
+    # the final dF at the stated 3 SE; the running maximum over the 5 correlated
+    # profile points at 3.5 (a family of tests, not one)
+    assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 3.5, z
     zm = (r["xi_mean"] - mu) / (r["xi_std"] / np.sqrt(r["n_samples"] / 20.0))
     assert np.max(np.abs(zm)) < 4.0
 
@@ -450,7 +547,7 @@ def test_sequential_harmonic_closed_form():
     r = estimators.estimate(p, xi, kept, with_appc=False)
     Fc, mu, var = quadrature.harmonic_closed_form(p["pot_kappa"], p["k"], p["kT"], p["lambda"])
     z = (r["dF_je"][-1] - (Fc[-1] - Fc[0])) / r["dF_je_se"][-1]
-    assert abs(z) < 3.5, z
+    assert abs(z) < 3.0, z
 
 
 def test_sequential_double_well_quadrature():
@@ -459,7 +556,7 @@ def test_sequential_double_well_quadrature():
     r = estimators.estimate(p, xi, kept, with_appc=False)
     F, mu, var = quadrature.restrained_1d(quadrature.double_well(), p["lambda"], p["k"], p["kT"])
     z = (r["dF_je"] - (F - F[0]))[1:] / r["dF_je_se"][1:]
-    assert abs(z[-1]) < 3.5 and np.max(np.abs(z)) < 4.0, z
+    assert abs(z[-1]) < 3.0 and np.max(np.abs(z)) < 4.0, z
 
 
 def test_sequential_frozen_replica_stays_frozen():
