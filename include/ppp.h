@@ -271,6 +271,25 @@ ppp_status ppp_workspace_size(const ppp_handle *h, size_t *bytes);
  * below ppp_workspace_size. */
 ppp_status ppp_run(ppp_handle *h, void *d_workspace, size_t bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ppp_run with
+ * the workspace taken from a device array the library holds, one per GPU, for
+ * the life of the process (PPP_STATIC_WORKSPACE_BYTES; each GPU the library runs
+ * on keeps it until the process ends), instead of a caller buffer.  The caller
+ * passes the handle and a stream; results come back through ppp_get_result as
+ * after ppp_run.  Makes no device or host allocation: no hipMalloc or hipFree,
+ * and no timing events (ppp_get_timings then reports NaN times unless an earlier
+ * ppp_run on the handle created them).  Every call on one GPU shares that GPU's
+ * array and leaves its contents there (the run clears what it accumulates into
+ * before it starts), so calls that overlap on one GPU -- two handles, or two
+ * streams, before the first one's ppp_get_result -- race and give wrong results.
+ * Single-problem handles only (PPP_E_UNSUPPORTED for batched ones);
+ * PPP_E_OUT_OF_MEMORY, before any device work and with the sizes in
+ * ppp_last_error, for a problem whose ppp_workspace_size exceeds
+ * PPP_STATIC_WORKSPACE_BYTES. */
+#define PPP_STATIC_WORKSPACE_BYTES (64u << 20)
+ppp_status ppp_run_static(ppp_handle *h, void *hip_stream);
+
 /* Incremental form of ppp_run (same protocol, Sec. III(ii)): begin (initial
  * state), advance by n steps (clamped to the steps left), finalize (reductions,
  * estimators and App. C on what has been sampled so far; an advance may follow

@@ -98,6 +98,7 @@ class ppp_adaptive(ctypes.Structure):
                 ("placement", ctypes.c_int32)]
 
 PPP_PLACE_LEARNED, PPP_PLACE_EXPLORED = 0, 1
+PPP_STATIC_WORKSPACE_BYTES = 64 << 20          # include/ppp.h
 
 
 _lib = None
@@ -122,6 +123,7 @@ def lib():
             "ppp_batch_create": ([ctypes.POINTER(ppp_problem), ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(H)], st),
             "ppp_workspace_size": ([H, ctypes.POINTER(ctypes.c_size_t)], st),
             "ppp_run": ([H, vp, ctypes.c_size_t, vp], st),
+            "ppp_run_static": ([H, vp], st),
             "ppp_begin": ([H, vp, ctypes.c_size_t, vp], st),
             "ppp_advance": ([H, ctypes.c_int64, vp], st),
             "ppp_finalize": ([H, vp], st),
@@ -156,7 +158,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["ppp_create", "ppp_batch_create", "ppp_workspace_size", "ppp_run", "ppp_begin",
+EXPORTED = ["ppp_create", "ppp_batch_create", "ppp_workspace_size", "ppp_run", "ppp_run_static", "ppp_begin",
             "ppp_advance",
             "ppp_finalize", "ppp_steps_done", "ppp_get_result", "ppp_batch_get_result", "ppp_get_timings",
             "ppp_checkpoint", "ppp_restore", "ppp_destroy", "ppp_status_string", "ppp_last_error",
@@ -251,6 +253,10 @@ def workspace(h, device="cuda"):
 
 def ppp_run(h, ws, stream=None):
     return _check(lib().ppp_run(h, _ptr(ws), ws.numel(), _stream(stream)), h, "ppp_run")
+
+
+def ppp_run_static(h, stream=None):
+    return _check(lib().ppp_run_static(h, _stream(stream)), h, "ppp_run_static")
 
 
 def ppp_begin(h, ws, stream=None):

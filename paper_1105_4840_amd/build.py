@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libppp.so")
-SOURCES = ["ppp_sim.hip", "ppp_reduce.hip", "ppp_mlp.hip", "ppp_probe.hip", "ppp_runtime.cpp",
+SOURCES = ["ppp_sim.hip", "ppp_reduce.hip", "ppp_mlp.hip", "ppp_probe.hip", "ppp_static.hip", "ppp_runtime.cpp",
            "ppp_adaptive.cpp"]
 ARCH = os.environ.get("PPP_OFFLOAD_ARCH", "gfx950")
 

@@ -1058,6 +1058,24 @@ ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, flo
 // ===========================================================================
 namespace ppp {
 
+void set_error(ppp_handle *h, const std::string &msg) {
+    if (h) h->err = msg;
+}
+
+ppp_status run_without_allocation(ppp_handle *h, void *ws, size_t bytes, void *stream) {
+    if (!h) return PPP_E_INVALID_ARG;
+    if (h->batch) return fail(h, PPP_E_UNSUPPORTED, "the allocation-free run takes single-problem handles");
+    if ((int64_t)bytes < h->ws_bytes)
+        return fail(h, PPP_E_OUT_OF_MEMORY, "problem needs " + std::to_string(h->ws_bytes) +
+                                                " workspace bytes, above the static workspace of " +
+                                                std::to_string(bytes));
+    hipStream_t st = (hipStream_t)stream;
+    ppp_status s;
+    if ((s = do_begin(h, ws, bytes, st, false)) != PPP_OK) return s;
+    if ((s = do_advance(h, INT64_MAX / 4, st)) != PPP_OK) return s;
+    return do_finalize(h, st);
+}
+
 size_t workspace_bytes_for(const ppp_problem *p) {
     ppp_handle *h = nullptr;
     if (ppp_create(p, &h) != PPP_OK) return 0;
