@@ -169,9 +169,10 @@ def dF_error_block(args, log=True):
     --ref-steps steps), the plain protocol with 21 uniform windows at the full budget
     of 2e9 replica-steps; learned placement at half and at the full budget; and, at
     the half budget, the two baselines that isolate what the surrogate adds: uniform
-    windows at the count the learned placement chose (all of the budget in
-    production), and the same exploration rounds and placement rule with sigma(lambda)
-    interpolated from the explored windows' sample sigma_i (no network)."""
+    windows at the count the learned placement chose, relaxing as long as its
+    production windows, all of the budget in production; and the same exploration
+    rounds and placement rule with sigma(lambda) interpolated from the explored
+    windows' sample sigma_i (no network)."""
     import numpy as np
     import paper_1105_4840_amd as ppp
     import ppp_inputs
@@ -210,12 +211,16 @@ def dF_error_block(args, log=True):
         rows[f"learned_{frac:g}budget"] = err(res, lam, ref_lam, ref, used)
         say(f"# dF block: learned at {frac:g} budget, {len(lam)} windows, {time.time() - t0:.1f} s")
         if frac == 0.5:
+            # uniform windows at the learned count, each relaxing as long as a learned
+            # production window (--min-steps), the replicas sized to spend the budget
             W = len(lam)
-            steps = int(0.5 * budget) // (W * 4096)
-            up = ppp_inputs.config_chain32(n_steps=steps, lam=np.linspace(3.0, 28.0, W))
+            steps = args.min_steps
+            reps = min(4096, int(0.5 * budget) // (W * steps))
+            steps = int(0.5 * budget) // (W * reps)
+            up = ppp_inputs.config_chain32(n_replicas=reps, n_steps=steps, lam=np.linspace(3.0, 28.0, W))
             u, _ = ppp.run(up)
             rows["uniform_at_learned_count_0.5budget"] = err(u, np.array(up["lambda"]), ref_lam, ref,
-                                                              W * 4096 * steps, {"steps": steps})
+                                                              W * reps * steps, {"steps": steps, "replicas": reps})
             e, lam_e, used_e = ppp.ppp_adaptive_run(base, dict(ad, budget_replica_steps=int(0.5 * budget),
                                                                placement="explored"))
             rows["explored_sigma_0.5budget"] = err(e, lam_e, ref_lam, ref, used_e)
