@@ -36,14 +36,20 @@ FP64_PEAK = 78.6e12
 # HBM traffic of one launch of the simulation kernel, from two rocprofv3 --pmc runs of
 # this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
 # same counter reads for a 1 GiB device-to-device copy in the same run (--pmc-copy-mib
-# 1024: FETCH_SIZE reads 529747.5 KiB -> x1.9794, WRITE_SIZE 1059107.1 KiB -> x0.9901).
+# 1024): the copy reads 1048576 KiB and writes as much, so a scale is 1048576 over the
+# copy's reading.  chain256: the second of two launches of 1000 steps (--profile-launches
+# 2), which reads the state the first one wrote, as every timed launch does.
 # A record holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain10": {"sources_sha1": "04fdcc61e43361cc039f1648b793919ae0c4150d", "kernel": "sim_chain<float,5,2>",
-                "fetch_kib": 175.0, "fetch_scale": 1.9794, "write_kib": 10146.03125, "write_scale": 0.9901},
+    "chain256": {"sources_sha1": "7cdaf40fda628876255dda9c9f029c35c47f445f", "kernel": "sim_chain<float,64,4>",
+                 "fetch_kib": 517151.0, "fetch_scale": 1048576 / 524308.0, "write_kib": 1028608.0,
+                 "write_scale": 1048576 / 1048576.0},
+    "chain10": {"sources_sha1": "7cdaf40fda628876255dda9c9f029c35c47f445f", "kernel": "sim_chain<float,5,2>",
+                "fetch_kib": 170.5, "fetch_scale": 1048576 / 524315.375, "write_kib": 10145.71875,
+                "write_scale": 1048576 / 1048576.0},
 }
-KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip", "ppp_shapes.hpp",
-                  "ppp_launch.hpp")
+KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_chain_force.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip",
+                  "ppp_shapes.hpp", "ppp_launch.hpp")
 
 
 def kernel_sources_digest():
@@ -381,18 +387,22 @@ def peak_study(args):
     stream = torch.cuda.current_stream(dev)
     n_blocks, iters = 16384, 16384
     out = torch.empty(n_blocks * 256, dtype=torch.float32, device=dev)
-    ppp.ppp_probe_valu(n_blocks, 64, out=out)                  # warm-up
-    torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ms = []
-    for _ in range(5):
-        t0.record(stream)
-        ppp.ppp_probe_valu(n_blocks, iters, out=out, stream=stream)
-        t1.record(stream)
-        t1.synchronize()
-        ms.append(t0.elapsed_time(t1))
     flops = 16.0 * iters * n_blocks * 256
-    fma = flops / (min(ms) * 1e-3) / 1e12
+    fma_ms = {}
+    for vgpr in (False, True):
+        ppp.ppp_probe_valu(n_blocks, 64, out=out, vgpr_operands=vgpr)       # warm-up
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(5):
+            t0.record(stream)
+            ppp.ppp_probe_valu(n_blocks, iters, out=out, stream=stream, vgpr_operands=vgpr)
+            t1.record(stream)
+            t1.synchronize()
+            ms.append(t0.elapsed_time(t1))
+        fma_ms[vgpr] = min(ms)
+    fma = flops / (fma_ms[False] * 1e-3) / 1e12
+    fma_v = flops / (fma_ms[True] * 1e-3) / 1e12
     nbytes = 1 << 30
     src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
@@ -408,9 +418,13 @@ def peak_study(args):
     gbs = 2.0 * nbytes / (min(cms) * 1e-3) / 1e9
     print(json.dumps({
         "study": "measured ceilings (context; roofline fractions use the published peaks)",
-        "fp32_fma": {"tflops": fma, "ms": min(ms), "flops": flops, "threads": n_blocks * 256, "chains_per_thread": 8,
+        "fp32_fma": {"tflops": fma, "ms": fma_ms[False], "operands": "b, c in scalar registers",
+                     "flops": flops, "threads": n_blocks * 256, "chains_per_thread": 8,
                      "published_packed_peak": FP32_PEAK / 1e12, "published_unpacked_rate": FP32_PEAK / 2e12,
-                     "frac_of_unpacked": fma / (FP32_PEAK / 2e12)},
+                     "frac_of_unpacked": fma / (FP32_PEAK / 2e12), "frac_of_peak": fma / (FP32_PEAK / 1e12)},
+        "fp32_fma_vgpr": {"tflops": fma_v, "ms": fma_ms[True], "operands": "b, c in vector registers",
+                          "frac_of_peak": fma_v / (FP32_PEAK / 1e12),
+                          "cycles_per_wave_instruction": 1024 * 2.4e9 * fma_ms[True] * 1e-3 / (flops / 128.0)},
         "hbm_copy": {"gb_per_s": gbs, "ms": min(cms), "bytes_moved": 2 * nbytes, "published_peak": 8000.0,
                      "frac": gbs / 8000.0},
     }))

@@ -348,10 +348,16 @@ ppp_status ppp_trajectory(ppp_handle *h, void *d_workspace, size_t bytes, int32_
 
 /* Raw Philox4x32-10 blocks and the kernels' normal deviates: for i < n,
  * counter (c0 + i, c1, c2, c3) under key seed.  d_words: device u32 [n][4];
- * d_normals: device fp64 [n][4] (fp64 Box-Muller; may be NULL);
- * d_normals32: device fp32 [n][4] (fp32 Box-Muller; may be NULL). */
+ * d_normals, d_normals32: device fp64 / fp32 [n][4], the four Box-Muller
+ * normals of a block (the 1-D model's noise: 32-bit uniforms in fp64, 23-bit
+ * in fp32); d_normals6, d_normals6_32: device fp64 / fp32 [n][6], the six
+ * normals of a block from 21-bit uniforms (the chain's noise, beads 2m and
+ * 2m + 1 of replica gid at step n sharing counter (gid, n, m, 0)).  Every
+ * output but d_words may be NULL.  Errors: PPP_E_INVALID_ARG for n < 0,
+ * PPP_E_DEVICE if the launch fails. */
 ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n,
-                      uint32_t *d_words, double *d_normals, float *d_normals32, void *hip_stream);
+                      uint32_t *d_words, double *d_normals, float *d_normals32, double *d_normals6,
+                      float *d_normals6_32, void *hip_stream);
 
 /* ---- learned window placement ------------------------------------------ */
 

@@ -60,6 +60,7 @@ def lib():
         pp = ctypes.POINTER(OracleProblem)
         L.oracle_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.oracle_normals4.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [dp]
+        L.oracle_normals6.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [dp]
         L.oracle_chain_forces.argtypes = [pp, dp, ctypes.c_double, dp, dp]
         L.oracle_chain_forces.restype = ctypes.c_double
         L.oracle_pot1d.argtypes = [pp, ctypes.c_double, ctypes.c_double, dp]
@@ -130,6 +131,13 @@ def philox(key, ctr):
 def normals4(seed, c0, c1, c2, c3):
     z = np.zeros(4)
     lib().oracle_normals4(int(seed), c0, c1, c2, c3, _dp(z))
+    return z
+
+
+def normals6(seed, c0, c1, c2, c3):
+    """Six normals of one block (the chain's noise: two beads per block)."""
+    z = np.zeros(6)
+    lib().oracle_normals6(int(seed), c0, c1, c2, c3, _dp(z))
     return z
 
 

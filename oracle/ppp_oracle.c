@@ -104,6 +104,41 @@ void oracle_normals4(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint3
     }
 }
 
+/* Six standard normals from one Philox block.  The 128 bits give six 21-bit
+ * integers: a_k = r_k >> 11 (k = 0..3), a_4 = (r_0 mod 2^11) 2^10 + (r_1 mod
+ * 2^10), a_5 = (r_2 mod 2^11) 2^10 + (r_3 mod 2^10); u_k = (a_k + 1/2) 2^-21,
+ * exact in fp64 and in fp32.  (z_{2p}, z_{2p+1}) = sqrt(-2 ln u_{2p})
+ * (cos 2 pi u_{2p+1}, sin 2 pi u_{2p+1}) for p = 0, 1, 2.  The smallest u is
+ * 2^-22, so |z| <= sqrt(44 ln 2) = 5.52; a normal lies beyond that with
+ * probability 3.4e-8. */
+void oracle_normals6(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, double z[6])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t r[4];
+    oracle_philox4x32_10(key, ctr, r);
+    const uint32_t a[6] = {r[0] >> 11, r[1] >> 11, r[2] >> 11, r[3] >> 11,
+                           ((r[0] & 0x7ffu) << 10) | (r[1] & 0x3ffu), ((r[2] & 0x7ffu) << 10) | (r[3] & 0x3ffu)};
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int p = 0; p < 3; ++p) {
+        double ua = ((double)a[2 * p] + 0.5) * (1.0 / 2097152.0);
+        double ub = ((double)a[2 * p + 1] + 0.5) * (1.0 / 2097152.0);
+        double rad = sqrt(-2.0 * log(ua));
+        z[2 * p] = rad * cos(two_pi * ub);
+        z[2 * p + 1] = rad * sin(two_pi * ub);
+    }
+}
+
+/* The three normals of chain bead i of replica gid at step n (n = 0: the
+ * initial velocities): beads 2m and 2m + 1 share the block with counter
+ * (gid, n, m, 0), the even bead taking z_0..z_2 and the odd one z_3..z_5. */
+static void bead_normals(uint64_t seed, uint32_t gid, uint32_t n, int i, double z[3])
+{
+    double z6[6];
+    oracle_normals6(seed, gid, n, (uint32_t)(i >> 1), 0u, z6);
+    for (int c = 0; c < 3; ++c) z[c] = z6[3 * (i & 1) + c];
+}
+
 /* The normal deviate eta_n of the 1-D model for replica gid at step n:
  * component n mod 4 of the block with counter (gid, n div 4, 0, 0). */
 static double eta_1d(uint64_t seed, uint32_t gid, int64_t n)
@@ -302,8 +337,8 @@ static int64_t run_replica_chain(const oracle_problem *p, int window, int replic
     const double sd_v = sqrt(p->kT / p->mass);
     /* Maxwell velocities of the mobile beads from counter step 0 */
     for (int i = 1; i < N; ++i) {
-        double z[4];
-        oracle_normals4(p->seed, gid, 0u, (uint32_t)i, 0u, z);
+        double z[3];
+        bead_normals(p->seed, gid, 0u, i, z);
         for (int c = 0; c < 3; ++c) v[3 * i + c] = sd_v * z[c];
     }
     const double xi_start = chain_xi(p, r);
@@ -316,8 +351,8 @@ static int64_t run_replica_chain(const oracle_problem *p, int window, int replic
     int64_t kept = 0;
     for (int64_t n = 1; n <= p->n_steps; ++n) {
         for (int i = 1; i < N; ++i) {              /* bead 0 stays fixed */
-            double z[4];
-            oracle_normals4(p->seed, gid, (uint32_t)n, (uint32_t)i, 0u, z);
+            double z[3];
+            bead_normals(p->seed, gid, (uint32_t)n, i, z);
             for (int c = 0; c < 3; ++c) {
                 int q = 3 * i + c;
                 v[q] += h * f[q] / p->mass;        /* B */
@@ -394,8 +429,8 @@ static void run_sequential_chain(const oracle_problem *p, int replica, double *x
     else oracle_default_helix(N, p->r0, r);
     const double sd_v = sqrt(p->kT / p->mass);
     for (int i = 1; i < N; ++i) {
-        double z[4];
-        oracle_normals4(p->seed, gid, 0u, (uint32_t)i, 0u, z);
+        double z[3];
+        bead_normals(p->seed, gid, 0u, i, z);
         for (int c = 0; c < 3; ++c) v[3 * i + c] = sd_v * z[c];
     }
     const double xi_start = chain_xi(p, r);
@@ -412,8 +447,8 @@ static void run_sequential_chain(const oracle_problem *p, int replica, double *x
         for (int64_t t = 1; t <= p->n_steps && !frozen; ++t) {
             const int64_t n = (int64_t)w * p->n_steps + t;
             for (int i = 1; i < N; ++i) {
-                double z[4];
-                oracle_normals4(p->seed, gid, (uint32_t)n, (uint32_t)i, 0u, z);
+                double z[3];
+                bead_normals(p->seed, gid, (uint32_t)n, i, z);
                 for (int c = 0; c < 3; ++c) {
                     int q = 3 * i + c;
                     v[q] += h * f[q] / p->mass;

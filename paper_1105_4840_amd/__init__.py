@@ -99,6 +99,7 @@ class ppp_adaptive(ctypes.Structure):
 
 PPP_PLACE_LEARNED, PPP_PLACE_EXPLORED = 0, 1
 PPP_STATIC_WORKSPACE_BYTES = 64 << 20          # include/ppp.h
+PPP_PROBE_SGPR_OPERANDS, PPP_PROBE_VGPR_OPERANDS = 0, 1   # include/ppp_probe.h
 
 
 _lib = None
@@ -139,8 +140,9 @@ def lib():
             "ppp_create_error": ([], ctypes.c_char_p),
             "ppp_eval_forces": ([H, vp, ctypes.c_size_t, vp, ctypes.c_int32, ctypes.c_double, vp, vp, vp], st),
             "ppp_trajectory": ([H, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp], st),
-            "ppp_philox": ([ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [ctypes.c_int32, vp, vp, vp, vp], st),
-            "ppp_probe_valu": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, vp, vp], st),
+            "ppp_philox": ([ctypes.c_uint64] + [ctypes.c_uint32] * 4 + [ctypes.c_int32, vp, vp, vp, vp, vp, vp], st),
+            "ppp_probe_valu": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_int32, vp, vp],
+                               st),
             "ppp_mlp_forward": ([vp, vp, ctypes.c_int32, vp, vp, vp], st),
             "ppp_mlp_grad": ([vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp, vp, vp], st),
             "ppp_mlp_adam": ([vp, vp, vp, vp, ctypes.c_float, ctypes.c_int32, vp], st),
@@ -366,26 +368,33 @@ def ppp_trajectory(h, ws, window, replica, n_steps, dof, stream=None):
 
 
 def ppp_philox(seed, c0, c1, c2, c3, n, device="cuda", stream=None):
-    """(words u32 as int64 [n,4], fp64 normals [n,4], fp32 normals [n,4]) for counters (c0+i, c1, c2, c3)."""
+    """(words u32 [n,4], fp64 normals [n,4], fp32 normals [n,4], fp64 normals [n,6], fp32 normals [n,6])
+    for counters (c0+i, c1, c2, c3): the 1-D model's four normals per block and the chain's six."""
     import torch
     words = torch.zeros((n, 4), dtype=torch.int32, device=device)
     z64 = torch.zeros((n, 4), dtype=torch.float64, device=device)
     z32 = torch.zeros((n, 4), dtype=torch.float32, device=device)
-    st = lib().ppp_philox(int(seed), c0, c1, c2, c3, int(n), _ptr(words), _ptr(z64), _ptr(z32), _stream(stream))
+    y64 = torch.zeros((n, 6), dtype=torch.float64, device=device)
+    y32 = torch.zeros((n, 6), dtype=torch.float32, device=device)
+    st = lib().ppp_philox(int(seed), c0, c1, c2, c3, int(n), _ptr(words), _ptr(z64), _ptr(z32), _ptr(y64), _ptr(y32),
+                          _stream(stream))
     _check(st, None, "ppp_philox")
-    return words.cpu().numpy().view(np.uint32), z64.cpu().numpy(), z32.cpu().numpy()
+    return (words.cpu().numpy().view(np.uint32), z64.cpu().numpy(), z32.cpu().numpy(), y64.cpu().numpy(),
+            y32.cpu().numpy())
 
 
-def ppp_probe_valu(n_blocks, iters, b=0.999999, c=1e-7, out=None, device="cuda", stream=None):
+def ppp_probe_valu(n_blocks, iters, b=0.999999, c=1e-7, out=None, device="cuda", stream=None, vgpr_operands=False):
     """Launches the fp32 FMA issue-rate probe (16 * iters flops per thread, n_blocks x 256
-    threads) on `stream` and returns its device output (one fp32 per thread)."""
+    threads) on `stream` and returns its device output (one fp32 per thread); b and c in
+    scalar registers, or in vector registers with vgpr_operands."""
     import torch
     n = int(n_blocks) * 256
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=device)
     if out.numel() < n or out.dtype != torch.float32:
         raise ValueError("ppp_probe_valu: out must hold n_blocks * 256 fp32 values")
-    _check(lib().ppp_probe_valu(int(n_blocks), int(iters), float(b), float(c), _ptr(out), _stream(stream)),
+    mode = PPP_PROBE_VGPR_OPERANDS if vgpr_operands else PPP_PROBE_SGPR_OPERANDS
+    _check(lib().ppp_probe_valu(int(n_blocks), int(iters), float(b), float(c), mode, _ptr(out), _stream(stream)),
            None, "ppp_probe_valu")
     return out
 

@@ -2,7 +2,7 @@
 // (device code of the simulation kernels; the parity hook for forces uses the
 // same routine).  Included after ppp_device.hpp, which supplies the lane
 // moves (pull_f, push_f), the working-precision reciprocal and length
-// (rcp_t, len_inv) and the noise (Normal4).
+// (rcp_t, len_inv) and the noise (Normal6).
 #pragma once
 
 namespace ppp {
@@ -237,11 +237,32 @@ struct ChainForce {
     }
 };
 
-// Noise of bead `bead` at step `step`: the first three normals of Philox block
-// (gid, step, bead, 0); step 0 gives the Maxwell velocities.
-template <typename T, int G, int B>
-__device__ __forceinline__ void chain_noise(const DevProblem &P, uint32_t gid, uint32_t step, int bead, T z[4]) {
-    Normal4<T>::get(P.seed, gid, step, (uint32_t)bead, 0u, z);
+// The noise of the lane's beads at step `step` (step 0: the Maxwell
+// velocities): beads 2m and 2m + 1 share Philox block (gid, step, m, 0), the
+// even bead taking its normals z_0..z_2 and the odd bead z_3..z_5.  Calls
+// fn(b, z) with the three normals z of owned bead b = 0..B-1.  A lane with an
+// even bead count owns whole pairs and draws B/2 blocks; otherwise each bead
+// draws its pair's block and keeps its half.
+template <typename T, int B, typename Fn>
+__device__ __forceinline__ void lane_noise(const DevProblem &P, uint32_t gid, uint32_t step, int i0, Fn &&fn) {
+    if constexpr (B % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) {
+            T z[6];
+            Normal6<T>::get(P.seed, gid, step, (uint32_t)((i0 >> 1) + q), 0u, z);
+            fn(2 * q, z);
+            fn(2 * q + 1, z + 3);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            T z[6];
+            Normal6<T>::get(P.seed, gid, step, (uint32_t)(i >> 1), 0u, z);
+            if (i & 1) { z[0] = z[3]; z[1] = z[4]; z[2] = z[5]; }
+            fn(b, z);
+        }
+    }
 }
 
 // One BAOAB step of the lane's owned beads (Leimkuhler-Matthews splitting):
@@ -255,18 +276,15 @@ __device__ __forceinline__ void baoab_step(const DevProblem &P, int g, int gbase
                                            T (&vx)[B], T (&vy)[B], T (&vz)[B], T (&fx)[B], T (&fy)[B], T (&fz)[B]) {
     const int N = P.n_beads;
     const int i0 = g * B;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
+    lane_noise<T, B>(P, gid, n, i0, [&](int b, const T *z) {
         const int i = i0 + b;
         if (i > 0 && i < N) {
-            T z[4];
-            chain_noise<T, G, B>(P, gid, n, i, z);
             vx[b] += hm * fx[b]; vy[b] += hm * fy[b]; vz[b] += hm * fz[b];
             px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
             vx[b] = c1 * vx[b] + c2sd * z[0]; vy[b] = c1 * vy[b] + c2sd * z[1]; vz[b] = c1 * vz[b] + c2sd * z[2];
             px[b] += h * vx[b]; py[b] += h * vy[b]; pz[b] += h * vz[b];
         }
-    }
+    });
     ChainForce<T, G, B, false>::compute(P, g, gbase, centre, kr, px, py, pz, fx, fy, fz, nullptr);
 #pragma unroll
     for (int b = 0; b < B; ++b) {

@@ -71,6 +71,56 @@ template <> struct Normal4<float> {
     }
 };
 
+// Six standard normals per Philox block, the noise of the chain (two beads
+// per block).  The 128 bits give six 21-bit integers: a_k = r_k >> 11 for
+// k = 0..3, a_4 = (r_0 mod 2^11) 2^10 + (r_1 mod 2^10) and a_5 likewise from
+// r_2 and r_3; u_k = (a_k + 1/2) 2^-21, exact in both precisions; Box-Muller on
+// (u_0, u_1), (u_2, u_3), (u_4, u_5).  Half a block per bead instead of one
+// block halves the Philox rounds of the chain kernels; |z| stays below
+// sqrt(44 ln 2) = 5.52 (the smallest u is 2^-22).
+template <typename T> struct Normal6;
+
+template <> struct Normal6<double> {
+    __device__ __forceinline__ static void get(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, double z[6]) {
+        const U4 r = philox(seed, c0, c1, c2, c3);
+        const uint32_t a[6] = {r.x >> 11, r.y >> 11, r.z >> 11, r.w >> 11, ((r.x & 0x7ffu) << 10) | (r.y & 0x3ffu),
+                               ((r.z & 0x7ffu) << 10) | (r.w & 0x3ffu)};
+        const double two_pi = 6.283185307179586476925286766559;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const double ua = ((double)a[2 * p] + 0.5) * 0x1p-21, ub = ((double)a[2 * p + 1] + 0.5) * 0x1p-21;
+            const double rad = sqrt(-2.0 * log(ua));
+            z[2 * p] = rad * cos(two_pi * ub);
+            z[2 * p + 1] = rad * sin(two_pi * ub);
+        }
+    }
+};
+
+template <> struct Normal6<float> {
+    // 1 + a 2^-21 is the float with bits 0x3f800000 | (a << 2); subtracting
+    // 1 - 2^-22 leaves (a + 1/2) 2^-21 exactly
+    __device__ __forceinline__ static float top21(uint32_t r) {
+        return __uint_as_float(((r >> 9) & 0x7ffffcu) | 0x3f800000u) - (1.0f - 0x1p-22f);
+    }
+    __device__ __forceinline__ static float low21(uint32_t hi, uint32_t lo) {
+        return __uint_as_float(((hi & 0x7ffu) << 12) | ((lo & 0x3ffu) << 2) | 0x3f800000u) - (1.0f - 0x1p-22f);
+    }
+    __device__ __forceinline__ static void get(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                               uint32_t c3, float z[6]) {
+        const U4 r = philox(seed, c0, c1, c2, c3);
+        const float m2ln2 = -2.0f * 0.69314718055994531f;
+        const float u[6] = {top21(r.x), top21(r.y), top21(r.z), top21(r.w), low21(r.x, r.y), low21(r.z, r.w)};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            // hardware log2, sqrt, and sin/cos of 2 pi times the argument
+            const float rad = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u[2 * p]));
+            z[2 * p] = rad * __builtin_amdgcn_cosf(u[2 * p + 1]);
+            z[2 * p + 1] = rad * __builtin_amdgcn_sinf(u[2 * p + 1]);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Reciprocal and length in the working precision: the hardware instructions
 // (about 1 ulp) in fp32, IEEE division and square root in fp64.

@@ -20,7 +20,7 @@ hipError_t launch_sim_persistent(const DevProblem *d_probs, const WorkItem *d_it
 hipError_t launch_eval(const DevProblem *d_probs, const double *coords, int n_rep, double centre, double *forces,
                        double *energy, int model, int precision, int G, int B, hipStream_t stream);
 hipError_t launch_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int n, uint32_t *words,
-                         double *z64, float *z32, hipStream_t stream);
+                         double *z64, float *z32, double *y64, float *y32, hipStream_t stream);
 
 // Zero the accumulators, histograms and work distributions of problems [0, n_probs);
 // clear n_tickets queue counters.

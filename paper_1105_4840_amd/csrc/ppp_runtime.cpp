@@ -1039,15 +1039,19 @@ ppp_status ppp_autotune(const char *path, void *ws, size_t bytes, void *stream) 
 }
 
 ppp_status ppp_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int32_t n, uint32_t *d_words,
-                      double *d_normals, float *d_normals32, void *stream) {
+                      double *d_normals, float *d_normals32, double *d_normals6, float *d_normals6_32, void *stream) {
     if (n < 0) return PPP_E_INVALID_ARG;
-    hipError_t e = launch_philox(seed, c0, c1, c2, c3, n, d_words, d_normals, d_normals32, (hipStream_t)stream);
+    hipError_t e = launch_philox(seed, c0, c1, c2, c3, n, d_words, d_normals, d_normals32, d_normals6, d_normals6_32,
+                                 (hipStream_t)stream);
     return e == hipSuccess ? PPP_OK : PPP_E_DEVICE;
 }
 
-ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, float *d_out, void *stream) {
+ppp_status ppp_probe_valu(int32_t n_blocks, int32_t iters, float b, float c, int32_t operands, float *d_out,
+                          void *stream) {
     if (n_blocks < 1 || iters < 1 || !d_out) return PPP_E_INVALID_ARG;
-    hipError_t e = launch_valu_probe(n_blocks, iters, b, c, d_out, (hipStream_t)stream);
+    if (operands != PPP_PROBE_SGPR_OPERANDS && operands != PPP_PROBE_VGPR_OPERANDS) return PPP_E_INVALID_ARG;
+    hipError_t e = launch_valu_probe(n_blocks, iters, b, c, operands == PPP_PROBE_VGPR_OPERANDS, d_out,
+                                     (hipStream_t)stream);
     return e == hipSuccess ? PPP_OK : PPP_E_DEVICE;
 }
 

@@ -9,13 +9,16 @@
 namespace ppp {
 
 __global__ void philox_blocks(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int n,
-                              uint32_t *__restrict__ words, double *__restrict__ z64, float *__restrict__ z32) {
+                              uint32_t *__restrict__ words, double *__restrict__ z64, float *__restrict__ z32,
+                              double *__restrict__ y64, float *__restrict__ y32) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const U4 r = philox(seed, c0 + (uint32_t)i, c1, c2, c3);
     if (words) { words[4 * i] = r.x; words[4 * i + 1] = r.y; words[4 * i + 2] = r.z; words[4 * i + 3] = r.w; }
     if (z64) { double z[4]; Normal4<double>::get(seed, c0 + (uint32_t)i, c1, c2, c3, z); for (int q = 0; q < 4; ++q) z64[4 * i + q] = z[q]; }
     if (z32) { float z[4]; Normal4<float>::get(seed, c0 + (uint32_t)i, c1, c2, c3, z); for (int q = 0; q < 4; ++q) z32[4 * i + q] = z[q]; }
+    if (y64) { double y[6]; Normal6<double>::get(seed, c0 + (uint32_t)i, c1, c2, c3, y); for (int q = 0; q < 6; ++q) y64[6 * i + q] = y[q]; }
+    if (y32) { float y[6]; Normal6<float>::get(seed, c0 + (uint32_t)i, c1, c2, c3, y); for (int q = 0; q < 6; ++q) y32[6 * i + q] = y[q]; }
 }
 
 #define PPP_DECLARE(GG, BB)                                                                                         \
@@ -101,9 +104,10 @@ hipError_t launch_eval(const DevProblem *d_probs, const double *coords, int n_re
 }
 
 hipError_t launch_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int n, uint32_t *words,
-                         double *z64, float *z32, hipStream_t stream) {
+                         double *z64, float *z32, double *y64, float *y32, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(philox_blocks, dim3((n + 255) / 256), dim3(256), 0, stream, seed, c0, c1, c2, c3, n, words, z64, z32);
+    hipLaunchKernelGGL(philox_blocks, dim3((n + 255) / 256), dim3(256), 0, stream, seed, c0, c1, c2, c3, n, words, z64, z32,
+                       y64, y32);
     return hipGetLastError();
 }
 

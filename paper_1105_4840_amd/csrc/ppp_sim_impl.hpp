@@ -304,13 +304,14 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
             const int i = i0 + b;
             if (i < N) { px[b] = (T)x0[3 * i]; py[b] = (T)x0[3 * i + 1]; pz[b] = (T)x0[3 * i + 2]; }
             else { px[b] = 0; py[b] = 0; pz[b] = (T)(P.pad_z0 + P.pad_dz * (i - N)); }
-            vx[b] = 0; vy[b] = 0; vz[b] = 0;
-            if (i > 0 && i < N) {
-                T z[4];
-                chain_noise<T, G, B>(P, gid, 0u, i, z);
-                vx[b] = (T)P.sd_v * z[0]; vy[b] = (T)P.sd_v * z[1]; vz[b] = (T)P.sd_v * z[2];
-            }
         }
+        lane_noise<T, B>(P, gid, 0u, i0, [&](int b, const T *z) {
+            const int i = i0 + b;
+            const bool mobile = i > 0 && i < N;
+            vx[b] = mobile ? (T)P.sd_v * z[0] : (T)0;
+            vy[b] = mobile ? (T)P.sd_v * z[1] : (T)0;
+            vz[b] = mobile ? (T)P.sd_v * z[2] : (T)0;
+        });
         if (lane_used && g == owner) acc_empty(acc);
     } else {
 #pragma unroll
@@ -395,9 +396,16 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
     }
 }
 
+// Waves per SIMD the compiler schedules the chain kernels for.  The 64x4
+// kernel keeps a replica's 16 pair distances and all its lane exchanges of a
+// round in flight (about 250 registers): it runs two waves per SIMD whatever
+// the schedule, and asked for more the scheduler trades that overlap away and
+// the kernel slows by a sixth.  Every other shape keeps the default (8).
+template <int G, int B> constexpr int chain_max_waves() { return (G == 64 && B == 4) ? 2 : 8; }
+
 // Direct launch: one work item per workgroup.
 template <typename T, int G, int B>
-__global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, chain_max_waves<G, B>()))) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
                                                 int n_items, char *__restrict__ ws, int64_t step_begin,
                                                 int64_t step_end, double *__restrict__ traj, int64_t traj_rep,
                                                 int lds_cap) {
@@ -417,7 +425,7 @@ __global__ __launch_bounds__(WG) void sim_chain(const DevProblem *__restrict__ p
 // Persistent launch: workgroups take items from a queue (atomic ticket) until
 // it is empty; items are ordered longest first by the host.
 template <typename T, int G, int B>
-__global__ __launch_bounds__(WG) void sim_chain_persistent(const DevProblem *__restrict__ probs,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, chain_max_waves<G, B>()))) void sim_chain_persistent(const DevProblem *__restrict__ probs,
                                                            const WorkItem *__restrict__ items, int n_items,
                                                            int *__restrict__ ticket, char *__restrict__ ws,
                                                            int lds_cap) {

@@ -193,13 +193,14 @@ void lane_traj(const DevProblem &P, const Input &in, std::vector<double> &traj) 
         const int i = i0 + b;
         if (i < N) { px[b] = (T)in.coords[3 * i]; py[b] = (T)in.coords[3 * i + 1]; pz[b] = (T)in.coords[3 * i + 2]; }
         else { px[b] = 0; py[b] = 0; pz[b] = (T)(P.pad_z0 + P.pad_dz * (i - N)); }
-        vx[b] = 0; vy[b] = 0; vz[b] = 0;
-        if (i > 0 && i < N) {
-            T z[4];
-            chain_noise<T, G, B>(P, gid, 0u, i, z);
-            vx[b] = (T)P.sd_v * z[0]; vy[b] = (T)P.sd_v * z[1]; vz[b] = (T)P.sd_v * z[2];
-        }
     }
+    lane_noise<T, B>(P, gid, 0u, i0, [&](int b, const T *z) {
+        const int i = i0 + b;
+        const bool mobile = i > 0 && i < N;
+        vx[b] = mobile ? (T)P.sd_v * z[0] : (T)0;
+        vy[b] = mobile ? (T)P.sd_v * z[1] : (T)0;
+        vz[b] = mobile ? (T)P.sd_v * z[2] : (T)0;
+    });
     const bool rec = lane_used && grp == 0;
     auto record = [&](int n) {
         if (!rec) return;

@@ -35,10 +35,17 @@ def _gpu():
 
 
 def test_philox_bits_and_normals():
+    """Philox words against the oracle's; the four normals of a block (1-D model)
+    and the six of the chain's noise in fp64 within 1e-13 of the oracle's.  fp32
+    four-normal deviates differ by the 23-bit uniforms (2e-4 relative); the six
+    fp32 normals use the oracle's 21-bit uniforms exactly, so only fp32 rounding
+    of log2, the product, sqrt and sin/cos of 2 pi u separates them: well below
+    1e-6 (1 + |z|) (9e-8 measured)."""
     _say("case philox")
     n = 4096
+    worst = 0.0
     for seed, c1, c2, c3 in [(0, 0, 0, 0), (123456789012345, 7, 11, 0), (2 ** 64 - 1, 2 ** 32 - 1, 5, 9)]:
-        w, z64, z32 = ppp.ppp_philox(seed, 1000, c1, c2, c3, n)
+        w, z64, z32, y64, y32 = ppp.ppp_philox(seed, 1000, c1, c2, c3, n)
         for i in range(0, n, 97):
             ref = oracle.philox([seed & 0xFFFFFFFF, seed >> 32], [1000 + i, c1, c2, c3])
             assert [int(x) for x in w[i]] == ref
@@ -46,9 +53,17 @@ def test_philox_bits_and_normals():
             assert np.max(np.abs(z64[i] - zr)) < 1e-13
             # fp32 deviates: 23-bit uniforms and hardware transcendentals
             assert np.max(np.abs(z32[i] - zr)) < 2e-4 * (1 + np.max(np.abs(zr)))
+            yr = oracle.normals6(seed, 1000 + i, c1, c2, c3)
+            assert np.max(np.abs(y64[i] - yr)) < 1e-13
+            err = np.abs(y32[i] - yr) / (1 + np.abs(yr))
+            worst = max(worst, float(np.max(err)))
+            assert np.max(err) < 1e-6, (i, y32[i], yr)
+    _say(f"  fp32 six-normal deviation: max |dz| / (1 + |z|) = {worst:.2e}")
     from scipy import stats
-    assert abs(z32.mean()) < 0.02 and abs(z32.var() - 1) < 0.03
-    assert stats.kstest(z32.ravel(), "norm").pvalue > 1e-4
+    for z in (z32, y32):
+        assert abs(z.mean()) < 0.02 and abs(z.var() - 1) < 0.03
+        assert stats.kstest(z.ravel(), "norm").pvalue > 1e-4
+    assert np.max(np.abs(y32)) <= np.sqrt(44 * np.log(2)) + 1e-5
 
 
 FORCE_CASES = [2, 3, 4, 9, 10, 13, 16, 23, 32, 37, 64, 100, 128, 200, 255, 256]
@@ -666,10 +681,13 @@ def test_every_kernel_shape_resumes_bit_exactly(shape, tmp_path, monkeypatch):
 def test_valu_probe_computes_its_chains():
     """The issue-rate probe does the arithmetic it is credited with: every thread's
     output is the sum of its 8 FMA chains, recomputed here in fp64 from the fp32
-    start values (fp32 rounding each step keeps it within 1e-5 relative)."""
+    start values (fp32 rounding each step keeps it within 1e-5 relative), with
+    its operands in scalar registers and, bit for bit the same, in vector ones."""
     _say("case valu probe")
     n_blocks, iters, b, c = 3, 50, 0.999, 1e-3
     out = ppp.ppp_probe_valu(n_blocks, iters, b=b, c=c).cpu().numpy().astype(np.float64)
+    out_v = ppp.ppp_probe_valu(n_blocks, iters, b=b, c=c, vgpr_operands=True).cpu().numpy().astype(np.float64)
+    assert np.array_equal(out, out_v)
     i = np.arange(n_blocks * 256)
     want = np.zeros_like(out)
     b32, c32 = float(np.float32(b)), float(np.float32(c))

@@ -72,6 +72,27 @@ def test_normals_statistics():
     assert np.max(np.abs(c - np.eye(4))) < 5.0 / np.sqrt(z.shape[0])
 
 
+def test_normals6_statistics():
+    """The chain's six normals per block (21-bit uniforms, two beads per block):
+    mean 0, variance 1, Gaussian (KS) in every slot, no correlation between any
+    two slots (the two beads of a block among them), and |z| below the bound
+    sqrt(44 ln 2) that the smallest uniform 2^-22 sets.  A wrong shift or mask
+    in the bit fields gives uniforms outside (0, 1) or shared bits, which these
+    checks catch."""
+    from scipy import stats
+    z = np.array([oracle.normals6(11, g, n, m, 0) for g in range(20) for n in range(100) for m in range(5)])
+    assert np.all(np.isfinite(z)) and np.max(np.abs(z)) < np.sqrt(44 * np.log(2))
+    assert abs(z.mean()) < 4.0 / np.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5.0 * np.sqrt(2.0 / z.size)
+    for k in range(6):
+        assert stats.kstest(z[:, k], "norm").pvalue > 1e-3, k
+    c = np.corrcoef(z.T)
+    assert np.max(np.abs(c - np.eye(6))) < 5.0 / np.sqrt(z.shape[0])
+    # squares of the slots are uncorrelated too (a shared radius would show here)
+    c2 = np.corrcoef((z ** 2).T)
+    assert np.max(np.abs(c2 - np.eye(6))) < 5.0 * np.sqrt(3.0 / z.shape[0])
+
+
 # --------------------------------------------------------------------------- forces
 
 
