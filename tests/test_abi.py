@@ -172,3 +172,16 @@ def test_batch_rejects_1d():
 
 def test_autotune_rejects_null_path():
     assert ppp.lib().ppp_autotune(None, None, 0, None) == ppp.PPP_E_INVALID_ARG
+
+
+def test_valu_probe_rejects_bad_arguments_before_any_launch():
+    """The issue-rate probe checks its arguments on the host: an unknown operand
+    form, no blocks, no steps or a NULL output are refused without a launch."""
+    import ctypes
+    L = ppp.lib()
+    dummy = ctypes.c_void_p(16)   # never dereferenced: every call below is refused first
+    assert L.ppp_probe_valu(1, 1, 1.0, 0.0, 7, dummy, None) == ppp.PPP_E_INVALID_ARG
+    assert L.ppp_probe_valu(1, 1, 1.0, 0.0, -1, dummy, None) == ppp.PPP_E_INVALID_ARG
+    assert L.ppp_probe_valu(0, 1, 1.0, 0.0, ppp.PPP_PROBE_VGPR_OPERANDS, dummy, None) == ppp.PPP_E_INVALID_ARG
+    assert L.ppp_probe_valu(1, 0, 1.0, 0.0, ppp.PPP_PROBE_SGPR_OPERANDS, dummy, None) == ppp.PPP_E_INVALID_ARG
+    assert L.ppp_probe_valu(1, 1, 1.0, 0.0, ppp.PPP_PROBE_SGPR_OPERANDS, None, None) == ppp.PPP_E_INVALID_ARG

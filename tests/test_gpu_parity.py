@@ -90,9 +90,19 @@ def test_chain_forces(n_beads, precision):
         # exact forces of those coordinates, so only the kernel's arithmetic is measured
         xc = conf[c] if precision == "fp64" else conf[c].astype(np.float32).astype(np.float64)
         etot, parts, fr = oracle.chain_forces(prob, xc, lam)
-        # bead 0 is held fixed: the kernel leaves the restraint's reaction off it
-        d = f[c, 1:] - fr[1:]
-        assert np.linalg.norm(d) <= tol * np.linalg.norm(fr[1:]), (c, np.linalg.norm(d), np.linalg.norm(fr[1:]))
+        # bead 0 is held fixed: the kernel leaves the restraint's reaction
+        # k (xi - lambda) dxi/dx_last off it (its bonded and LJ forces stay)
+        want = fr.copy()
+        end = xc[-1] - xc[0]
+        if prob.get("rc_mode", 0) == 1:
+            xi, dxi = end[2], np.array([0.0, 0.0, 1.0])
+        else:
+            xi = np.linalg.norm(end)
+            dxi = end / xi
+        want[0] -= prob["k"] * (xi - lam) * dxi
+        d = f[c] - want
+        assert np.linalg.norm(d) <= tol * np.linalg.norm(want), (c, np.linalg.norm(d), np.linalg.norm(want))
+        assert np.linalg.norm(d[0]) <= tol * np.linalg.norm(want), (c, d[0])
         scale = np.sum(np.abs(parts)) + 1.0
         assert abs(e[c, 0] - etot) <= tol * scale
         assert np.all(np.abs(e[c, 1:] - parts) <= tol * scale)
