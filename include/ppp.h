@@ -314,7 +314,14 @@ ppp_status ppp_get_timings(const ppp_handle *h, ppp_timings *out);
 /* Replica state, accumulators and step counter after the last begin/advance.
  * host_buf == NULL: *bytes receives the size.  ppp_restore puts a checkpoint
  * of an identical problem back into d_workspace; advancing from it gives the
- * same results as an uninterrupted run (the noise is a function of the step). */
+ * same results as an uninterrupted run (the noise is a function of the step).
+ * Layout: 8 bytes of magic, the steps done (int64), then per problem its
+ * replica states first: for replica gid = window * n_replicas + replica, a
+ * chain holds 6 * n_pad values of the working precision (fp32 or fp64): x of
+ * the n_pad bead slots, then y, z, v_x, v_y, v_z, with n_pad = lanes x beads
+ * per lane of the kernel shape (ppp_timings.variant_*; slots from n_beads on
+ * are padding); a 1-D replica holds x and 0.  Accumulators and histograms
+ * follow, in the library's own layout. */
 ppp_status ppp_checkpoint(ppp_handle *h, void *host_buf, size_t *bytes);
 ppp_status ppp_restore(ppp_handle *h, void *d_workspace, size_t ws_bytes, const void *host_buf,
                        size_t bytes, void *hip_stream);

@@ -1,0 +1,87 @@
+"""Full-size parity in the launch the bench times (needs an MI355X): the
+10-bead workload (21 windows x 1024 replicas) and the 256-bead workload (41
+windows x 4096 replicas), fp32, advanced by one launch of a few steps over
+every replica, as `bench.py` launches them.  The state of sampled replicas is
+read from the checkpoint (layout in include/ppp.h) and compared with the fp64
+oracle's trajectory of the same replica: the first and last replica of the
+grid, both sides of a work item's end and of a window boundary.  The fp32
+state starts from fp32-rounded coordinates (the 256-bead helix reaches 100,
+where fp32 values are 7.6e-6 apart) and takes fp32 forces (1e-5) and normals
+(1e-7) for a few steps of dt = 0.005, so it stays within 1e-4 of the fp64
+trajectory (measured: 1.1e-6 and 2.4e-5); a replica read at the wrong place,
+run on the wrong noise stream or from the wrong start state would be off by
+1e-2 or more (the start velocities alone move a bead 0.025 in 5 steps)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1105_4840_amd as ppp
+import ppp_inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _run_and_sample(prob, steps, picks):
+    h = ppp.ppp_create(prob)
+    try:
+        ws = ppp.workspace(h)
+        ppp.ppp_begin(h, ws)
+        ppp.ppp_advance(h, steps)
+        ppp.ppp_finalize(h)          # reductions only: the replica state stays as advanced
+        torch.cuda.synchronize()
+        tim = ppp.ppp_get_timings(h)
+        blob = ppp.ppp_checkpoint(h)
+    finally:
+        ppp.ppp_destroy(h)
+    assert int(np.frombuffer(blob, dtype=np.int64, count=1, offset=8)[0]) == steps
+    n_pad = int(tim["variant_lanes"]) * int(tim["variant_beads_per_lane"])
+    n_rep = len(prob["lambda"]) * prob["n_replicas"]
+    state = np.frombuffer(blob, dtype=np.float32, count=n_rep * 6 * n_pad, offset=16).reshape(n_rep, 6, n_pad)
+    n = prob["n_beads"]
+    out = {}
+    for gid in picks:
+        out[gid] = state[gid, 0:3, :n].T.astype(np.float64)
+    return out, (tim["variant_lanes"], tim["variant_beads_per_lane"])
+
+
+def _check(prob, steps, picks, name):
+    got, shape = _run_and_sample(prob, steps, picks)
+    R = prob["n_replicas"]
+    worst = 0.0
+    for gid, x in got.items():
+        w, r = divmod(gid, R)
+        ref = oracle.trajectory(dict(prob, precision="fp64"), w, r, steps)[-1].reshape(-1, 3)
+        err = float(np.max(np.abs(x - ref)))
+        worst = max(worst, err)
+        assert err < 1e-4, (name, gid, err)
+    _say(f"  {name} (shape {shape[0]}x{shape[1]}): {len(picks)} sampled replicas after {steps} steps, "
+         f"max |x_gpu - x_oracle| = {worst:.2e}")
+
+
+def test_chain10_full_size_sampled_replicas():
+    prob = ppp_inputs.config_chain10()
+    _say("case full-size chain10: 21 windows x 1024 replicas, one launch of 20 steps")
+    # items hold 48 consecutive replicas (5x2 shape, 12 per wavefront); window 1 starts at 1024
+    _check(prob, 20, [0, 47, 48, 1023, 1024, 10 * 1024 + 517, 21 * 1024 - 1], "chain10")
+
+
+def test_chain256_full_size_sampled_replicas():
+    prob = ppp_inputs.config_chain256()
+    _say("case full-size chain256: 41 windows x 4096 replicas, one launch of 5 steps")
+    # items hold 4 consecutive replicas (64x4 shape, one per wavefront); window 1 starts at 4096
+    _check(prob, 5, [0, 3, 4, 4095, 4096, 20 * 4096 + 1234, 41 * 4096 - 1], "chain256")
