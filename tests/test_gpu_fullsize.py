@@ -1,6 +1,6 @@
 """Full-size parity in the launch the bench times (needs an MI355X): the
-10-bead workload (21 windows x 1024 replicas) and the 256-bead workload (41
-windows x 4096 replicas), fp32, advanced by one launch of a few steps over
+10-bead workload (21 windows x 1024 replicas), the 32-bead one (21 x 4096)
+and the 256-bead one (41 x 4096), fp32, advanced by one launch of a few steps over
 every replica, as `bench.py` launches them.  The state of sampled replicas is
 read from the checkpoint (layout in include/ppp.h) and compared with the fp64
 oracle's trajectory of the same replica: the first and last replica of the
@@ -85,3 +85,10 @@ def test_chain256_full_size_sampled_replicas():
     _say("case full-size chain256: 41 windows x 4096 replicas, one launch of 5 steps")
     # items hold 4 consecutive replicas (64x4 shape, one per wavefront); window 1 starts at 4096
     _check(prob, 5, [0, 3, 4, 4095, 4096, 20 * 4096 + 1234, 41 * 4096 - 1], "chain256")
+
+
+def test_chain32_full_size_sampled_replicas():
+    prob = ppp_inputs.config_chain32()
+    _say("case full-size chain32: 21 windows x 4096 replicas, one launch of 10 steps")
+    # items hold 16 consecutive replicas (16x2 shape, 4 per wavefront); window 1 starts at 4096
+    _check(prob, 10, [0, 15, 16, 4095, 4096, 13 * 4096 + 2222, 21 * 4096 - 1], "chain32")
