@@ -91,3 +91,38 @@ def test_crooks_estimate_matches_quadrature_on_1d_workload():
     dWb = p["w_bin"]
     assert np.all(np.abs(res["dF_rev_hist"] - exact) < 4.0 * res["dF_je_se"] + j * dWb + 0.01)
     assert res["crooks_ovl"][0] == 1.0 and res["crooks_ovl"][-1] < res["crooks_ovl"][1] < 1.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_baoab_harmonic_position_variance_is_exact(precision):
+    """The kernels' BAOAB with the chain's noise against a closed form: a
+    two-bead chain with no bond, the projection reaction coordinate (xi = z_1 -
+    z_0) and the restraint as the only force is a harmonic oscillator in z with
+    K = k, whose sampled position variance BAOAB gets exactly, kT/K, at any
+    stable step.  At k dt^2/4 = 0.45 other splittings are far off (ABOBA: 1.82
+    kT/K), and a noise amplitude off by a factor (1 + e) moves the variance by
+    (1 + e)^2.  16 windows x 4096 replicas x 1000 samples; every window has the
+    same variance, so the spread of the 16 window variances gives the error of
+    their mean whatever the samples' correlation."""
+    k, dt, R, S = 20.0, 0.3, 4096, 16
+    p = ppp_inputs.config_chain_small(2, n_replicas=R, n_steps=21000, n_windows=S, seed=9, precision=precision)
+    lam = np.linspace(-1.0, 1.0, S)
+    p.update({"k_bond": 0.0, "k_angle": 0.0, "lj_eps": 0.0, "rc_mode": 1, "k": k, "dt": dt,
+              "lambda": lam.tolist(), "init_coords": [0.0, 0.0, 0.0, 1.0, 0.0, 0.25],
+              "n_equil": 1000, "sample_every": 20})
+    p.update(ppp_inputs._hist_spec(-4.0, 4.0, 1024))
+    _say(f"case BAOAB harmonic variance {precision}: {S} windows x {R} replicas, k dt^2/4 = {k * dt * dt / 4:.2f}")
+    res, _ = ppp.run(p)
+    assert int(res["n_blown_up"].sum()) == 0
+    assert np.all(res["n_samples"] == R * 1000)
+    var = np.asarray(res["xi_std"]) ** 2
+    mu = np.asarray(res["xi_mean"])
+    want = p["kT"] / k
+    se = var.std(ddof=1) / np.sqrt(S)
+    _say(f"  mean variance {var.mean():.6f} (kT/k = {want:.6f}, se {se:.1e}); "
+         f"max |mean - lambda| {np.max(np.abs(mu - lam)):.1e}")
+    assert abs(var.mean() - want) < 4 * se
+    assert abs(var.mean() - want) < 2e-3 * want
+    # each window alone, against a 1% band (about eight times its own error)
+    assert np.all(np.abs(var - want) < 0.01 * want)
+    assert np.all(np.abs(mu - lam) < 5e-3)
