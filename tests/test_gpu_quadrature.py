@@ -126,3 +126,32 @@ def test_baoab_harmonic_position_variance_is_exact(precision):
     # each window alone, against a 1% band (about eight times its own error)
     assert np.all(np.abs(var - want) < 0.01 * want)
     assert np.all(np.abs(mu - lam) < 5e-3)
+
+
+@pytest.mark.parametrize("integrator,name", [(0, "LM"), (1, "EM")])
+def test_overdamped_harmonic_variance_closed_form(integrator, name):
+    """The 1-D kernel's overdamped schemes against closed forms on a harmonic
+    well of total stiffness K = kappa + k at K dt = 0.6: Leimkuhler-Matthews
+    keeps the exact variance kT/K at any step; Euler-Maruyama samples
+    kT/(K (1 - K dt/2)), here 1.43 kT/K.  16 windows x 4096 replicas; every
+    window has the same variance, so the spread of the window variances gives
+    the error of their mean."""
+    K, dt, R, S = 30.0, 0.02, 4096, 16
+    p = ppp_inputs.config_harmonic_1d(kappa=K - 10.0, k=10.0, n_replicas=R, n_steps=21000, seed=4)
+    lam = np.linspace(-1.0, 1.0, S)
+    p.update({"lambda": lam.tolist(), "dt": dt, "integrator_1d": integrator, "init_coords": [0.0],
+              "n_equil": 1000, "sample_every": 20})
+    p.update(ppp_inputs._hist_spec(-3.0, 3.0, 1024))
+    _say(f"case overdamped harmonic variance {name}: {S} windows x {R} replicas, K dt = {K * dt:.2f}")
+    res, _ = ppp.run(p)
+    var = np.asarray(res["xi_std"]) ** 2
+    mu = np.asarray(res["xi_mean"])
+    want = p["kT"] / K if integrator == 0 else p["kT"] / (K * (1.0 - K * dt / 2.0))
+    mean_want = p["k"] * lam / K
+    se = var.std(ddof=1) / np.sqrt(S)
+    _say(f"  mean variance {var.mean():.6f} (closed form {want:.6f}, se {se:.1e}); "
+         f"max |mean - k lambda/K| {np.max(np.abs(mu - mean_want)):.1e}")
+    assert abs(var.mean() - want) < 4 * se
+    assert abs(var.mean() - want) < 2e-3 * want
+    assert np.all(np.abs(var - want) < 0.01 * want)
+    assert np.all(np.abs(mu - mean_want) < 5e-3)
