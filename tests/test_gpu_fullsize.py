@@ -92,3 +92,30 @@ def test_chain32_full_size_sampled_replicas():
     _say("case full-size chain32: 21 windows x 4096 replicas, one launch of 10 steps")
     # items hold 16 consecutive replicas (16x2 shape, 4 per wavefront); window 1 starts at 4096
     _check(prob, 10, [0, 15, 16, 4095, 4096, 13 * 4096 + 2222, 21 * 4096 - 1], "chain32")
+
+
+def test_chain256_full_size_chunked_advance_is_bit_identical():
+    """The bench times the 256-bead workload in chunks of one launch each; the
+    state after 6 steps in one launch and after 2 + 4 steps in two launches
+    (41 x 4096 replicas, fp32) is the same to the last bit: every replica's
+    positions and velocities, its accumulators and the histograms."""
+    prob = ppp_inputs.config_chain256()
+    _say("case full-size chain256: 6 steps in one launch against 2 + 4 in two")
+    blobs = []
+    for chunks in ([6], [2, 4]):
+        h = ppp.ppp_create(prob)
+        try:
+            ws = ppp.workspace(h)
+            ppp.ppp_begin(h, ws)
+            for c in chunks:
+                ppp.ppp_advance(h, c)
+            torch.cuda.synchronize()
+            blobs.append(ppp.ppp_checkpoint(h))
+            del ws
+        finally:
+            ppp.ppp_destroy(h)
+    a, b = (np.frombuffer(x, dtype=np.uint8) for x in blobs)
+    assert a.size == b.size and a.size > 10**9          # 167936 replicas x 6 x 256 fp32 = 1.03e9 B of state
+    diff = int(np.count_nonzero(a != b))
+    _say(f"  {a.size / 1e9:.3f} GB of state, accumulators and histograms; bytes that differ: {diff}")
+    assert diff == 0
