@@ -320,7 +320,8 @@ ppp_status ppp_get_timings(const ppp_handle *h, ppp_timings *out);
  * chain holds 6 * n_pad values of the working precision (fp32 or fp64): x of
  * the n_pad bead slots, then y, z, v_x, v_y, v_z, with n_pad = lanes x beads
  * per lane of the kernel shape (ppp_timings.variant_*; slots from n_beads on
- * are padding); a 1-D replica holds x and 0.  Accumulators and histograms
+ * are padding); a 1-D replica holds x and the normal deviate of the last
+ * step (the Leimkuhler-Matthews scheme uses it again).  Accumulators and histograms
  * follow, in the library's own layout. */
 ppp_status ppp_checkpoint(ppp_handle *h, void *host_buf, size_t *bytes);
 ppp_status ppp_restore(ppp_handle *h, void *d_workspace, size_t ws_bytes, const void *host_buf,
