@@ -403,9 +403,23 @@ __device__ __forceinline__ void run_chain_item(const DevProblem &P, const WorkIt
 // the kernel slows by a sixth.  Every other shape keeps the default (8).
 template <int G, int B> constexpr int chain_max_waves() { return (G == 64 && B == 4) ? 2 : 8; }
 
+// Least waves per SIMD a direct launch is compiled for.  Left to itself the
+// compiler lands the fp32 kernels of chains longer than ten beads a few
+// registers above a wave boundary (16x2: 147 VGPRs, three waves; 3x4, 4x4 and
+// 8x4..32x4: 171-173, two waves).  Asked for one wave more they fit under it
+// (128, 168) without spilling and run 5-11% faster on 12- to 128-bead chains,
+// with the same machine arithmetic.  The 5x2 kernel keeps the default: the
+// 10-bead workload gives each SIMD fewer than two waves, and the tighter
+// budget costs it 4%.  The persistent kernel keeps one: its item loop holds
+// the fp64 exponential's constants in registers for the whole launch, and at
+// these floors it spills.
+template <typename T, int G, int B> constexpr int chain_min_waves() {
+    return sizeof(T) != 4 ? 1 : (B == 2 && G >= 8) ? 4 : (B == 4 && G >= 3 && G <= 32) ? 3 : 1;
+}
+
 // Direct launch: one work item per workgroup.
 template <typename T, int G, int B>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(1, chain_max_waves<G, B>()))) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(chain_min_waves<T, G, B>(), chain_max_waves<G, B>()))) void sim_chain(const DevProblem *__restrict__ probs, const WorkItem *__restrict__ items,
                                                 int n_items, char *__restrict__ ws, int64_t step_begin,
                                                 int64_t step_end, double *__restrict__ traj, int64_t traj_rep,
                                                 int lds_cap) {
