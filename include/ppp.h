@@ -100,9 +100,9 @@ typedef struct {
     const double *init_coords;   /* host, optional: 1-D [1] or chain [3 n_beads]; NULL: x_o =
                                     lambda_1 (1-D) or an ideal helix (chain); copied at create */
     double xi_min, xi_bin;       /* histogram of xi: bin b = floor((xi - xi_min)/xi_bin) */
-    int32_t xi_nbins;            /* K >= 1 */
+    int32_t xi_nbins;            /* K in [1, 2^26] */
     double w_bin;                /* work-distribution bin width dW > 0 */
-    int32_t w_half_bins;         /* M >= 0: 2M+1 work bins; 0 disables App. C */
+    int32_t w_half_bins;         /* M in [0, 5e7]: 2M+1 work bins; 0 disables App. C */
     int32_t n_jack_blocks;       /* jackknife blocks B in [0, 4096] (0: 32); above n_replicas: n_replicas */
     double xi_bound;             /* |xi| above this freezes a replica (<= 0: 1e4) */
     uint32_t flags;              /* 0, or PPP_FLAG_SEQUENTIAL or PPP_FLAG_FREE_ENSEMBLE */

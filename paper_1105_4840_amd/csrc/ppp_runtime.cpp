@@ -137,7 +137,8 @@ ppp_status validate(const ppp_problem *p, std::string &msg) {
     // samples taken while the centre still moves would be charged the work and the
     // window mean of the fixed lambda_i (Eqs. 9, 14): the pull must end before sampling
     if (p->n_pull > p->n_equil) { msg = "need n_pull <= n_equil (no samples while the centre moves)"; return PPP_E_INVALID_ARG; }
-    if (p->xi_nbins < 1) { msg = "xi_nbins must be >= 1"; return PPP_E_INVALID_ARG; }
+    // the bin loops step in int by up to 256 at a time, so K stays far from 2^31
+    if (p->xi_nbins < 1 || p->xi_nbins > (1 << 26)) { msg = "xi_nbins must be in [1, 2^26]"; return PPP_E_INVALID_ARG; }
     if (!finite_pos(p->xi_bin) || !std::isfinite(p->xi_min)) { msg = "xi_bin must be > 0, xi_min finite"; return PPP_E_INVALID_ARG; }
     if (p->w_half_bins < 0 || p->w_half_bins > 50000000) { msg = "w_half_bins out of range"; return PPP_E_INVALID_ARG; }
     if (p->w_half_bins > 0 && !finite_pos(p->w_bin)) { msg = "w_bin must be > 0"; return PPP_E_INVALID_ARG; }

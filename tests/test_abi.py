@@ -51,6 +51,9 @@ def _status(prob):
     lambda p: p.update(sample_every=0),
     lambda p: p.update(n_equil=p["n_steps"]),
     lambda p: p.update(xi_nbins=0),
+    lambda p: p.update(xi_nbins=(1 << 26) + 1),
+    lambda p: p.update(xi_nbins=2 ** 31 - 1),
+    lambda p: p.update(w_half_bins=50000001),
     lambda p: p.update(xi_bin=0.0),
     lambda p: p.update(w_bin=0.0),
     lambda p: p.update(n_blocks=10 ** 6),
