@@ -10,7 +10,9 @@ where fp32 values are 7.6e-6 apart) and takes fp32 forces (1e-5) and normals
 (1e-7) for a few steps of dt = 0.005, so it stays within 1e-4 of the fp64
 trajectory (measured: 1.1e-6 and 2.4e-5); a replica read at the wrong place,
 run on the wrong noise stream or from the wrong start state would be off by
-1e-2 or more (the start velocities alone move a bead 0.025 in 5 steps)."""
+1e-2 or more (the start velocities alone move a bead 0.025 in 5 steps).
+The uneven batch runs whole, in its one graph launch, and sampled problems
+are checked against their own single runs bit for bit."""
 import sys
 
 import numpy as np
@@ -119,3 +121,47 @@ def test_chain256_full_size_chunked_advance_is_bit_identical():
     diff = int(np.count_nonzero(a != b))
     _say(f"  {a.size / 1e9:.3f} GB of state, accumulators and histograms; bytes that differ: {diff}")
     assert diff == 0
+
+
+def test_batch_full_size_matches_single_runs():
+    """The uneven batch at full size (64 chains, 2.7e10 replica-steps) in the one
+    graph launch `bench.py --workload batch` times: the cheapest problem of each
+    chain-length class (up to 8, 12, 16, 32, 64 and 128 beads, so each kernel
+    shape group of the graph is sampled) reproduces its own single run bit for
+    bit in every output, and no replica of the batch is frozen.  A replica run on
+    another problem's parameters, noise stream or window, or an item that a
+    persistent workgroup skipped or ran twice, changes these outputs."""
+    probs = ppp_inputs.batched_instances()
+    edges = (8, 10, 12, 16, 32, 64, 128)
+    pick = {}
+    for i, p in enumerate(probs):
+        n = p["n_beads"]
+        cls = next(e for e in edges if n <= e)
+        cost = len(p["lambda"]) * p["n_replicas"] * p["n_steps"] * n * n
+        if cls not in pick or cost < pick[cls][1]:
+            pick[cls] = (i, cost)
+    sample = sorted(i for i, _ in pick.values())
+    _say(f"case full-size batch: 64 chains in one graph; sampled problems {sample} "
+         f"(beads {[probs[i]['n_beads'] for i in sample]})")
+    h = ppp.ppp_batch_create(probs)
+    try:
+        ws = ppp.workspace(h)
+        ppp.ppp_run(h, ws)
+        torch.cuda.synchronize()
+        _say(f"  graph: {ppp.ppp_get_timings(h)['sim_ms']:.0f} ms")
+        batch = {i: ppp.ppp_batch_get_result(h, probs[i], i) for i in range(len(probs))}
+        del ws
+    finally:
+        ppp.ppp_destroy(h)
+    frozen = sum(int(np.sum(r["n_blown_up"])) for r in batch.values())
+    assert frozen == 0, frozen
+    keys = ("dF_je", "dF_fluct", "dF_gauss", "dF_je_se", "xi_mean", "xi_std", "n_samples", "xi_hist",
+            "dF_je_hist", "work_hist", "overlap_ovl", "kish_frac", "work_hist_rev", "dF_crooks", "sigma_lsq")
+    for i in sample:
+        single = ppp.run(probs[i])[0]
+        for key in keys:
+            a, b = np.asarray(batch[i][key]), np.asarray(single[key])
+            same = np.array_equal(a, b, equal_nan=True) if np.issubdtype(a.dtype, np.floating) \
+                else np.array_equal(a, b)
+            assert same, (i, key)
+    _say(f"  {len(sample)} problems equal to their single runs in {len(keys)} outputs each")
