@@ -243,6 +243,21 @@ def test_run_parity_fp64(case):
     _compare_runs(prob, res, ref)
 
 
+def test_run_parity_fp64_1d_full_size():
+    """The 1-D double-well workload at its full size and as the bench runs it
+    (21 windows x 256 replicas x 20000 LM steps, fp64, App. C over 2M+1 = 30001
+    work bins), element by element against the oracle.  Every window's restrained
+    potential is strictly convex (U'' = 60x^2 - 20 + k = 60x^2 + 30 at k = 50), so
+    a replica's two fp64 trajectories stay within rounding of each other for the
+    whole run and every sample falls in the same bin."""
+    prob = ppp_inputs.config_1d()
+    _say("case run 1d-full: 21 windows x 256 replicas x 20000 steps, fp64")
+    res, tim = ppp.run(prob)
+    xi, kept, _ = oracle.run(prob)
+    ref = estimators.estimate(prob, xi, kept)
+    _compare_runs(prob, res, ref)
+
+
 def _edge_case(name):
     if name == "smallest":          # N = 2, two windows, one replica, one histogram bin, no App. C
         p = ppp_inputs.config_chain_small(2, n_replicas=1, n_steps=500, n_windows=2, precision="fp64")
