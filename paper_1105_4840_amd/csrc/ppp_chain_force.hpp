@@ -14,6 +14,15 @@ template <typename T, int G, int B, bool ENERGY>
 struct ChainForce {
     // groups of at most 6 lanes run no Newton-3 rounds beyond round 2
     static constexpr bool kHaloFromRound1 = G > 1 && (G - 1) / 2 <= 2;
+    // Small groups of two-bead lanes (5x2, 6x2), where the bonded terms are a
+    // sixth of the step, mask the bonds beyond the chain's ends and the halo
+    // forces of the group's edge lanes with 0/1 factors instead of selects: a
+    // select reads a lane mask from scalar registers and issues at about half
+    // the rate of a vector-register multiply or FMA, and an add followed by a
+    // select becomes one FMA.  Multiplying by 1 is exact, so the forces are the
+    // same.  The factors stay in vector registers for the whole loop, which the
+    // kernels compiled for more waves per SIMD cannot spare.
+    static constexpr bool kMaskFactors = G > 1 && G <= 6 && B == 2;
 
     // Lennard-Jones between bead sets a (owned) and b; N3: also accumulate reaction on b.
     template <bool N3, bool MASK>
@@ -171,6 +180,7 @@ struct ChainForce {
             else { x = hnx; y = hny; z = hnz; }
         };
         T Dx[B + 1], Dy[B + 1], Dz[B + 1];
+        const T m_next = g + 1 < G ? (T)1 : (T)0, m_prev = g > 0 ? (T)1 : (T)0;
         T ux = 0, uy = 0, uz = 0, ail = 0;   // previous bond (t-1 -> t): unit vector, inverse length
         bool avalid = false;
 #pragma unroll
@@ -183,14 +193,21 @@ struct ChainForce {
             const bool bvalid = i >= 0 && i + 1 < N;
             // a bond outside the chain gets unit length so its masked terms stay finite
             T bl, bil;
-            len_inv(bvalid ? bx * bx + by * by + bz * bz : (T)1, bl, bil);
+            const T mb = bvalid ? (T)1 : (T)0;
+            if constexpr (kMaskFactors) {
+                const T b2 = bx * bx + by * by + bz * bz;
+                len_inv(b2 * mb + ((T)1 - mb), bl, bil);
+            } else {
+                len_inv(bvalid ? bx * bx + by * by + bz * bz : (T)1, bl, bil);
+            }
             const T vx = bx * bil, vy = by * bil, vz = bz * bil;
             if (t == 0) {
                 Dx[0] = 0; Dy[0] = 0; Dz[0] = 0;
             } else {
                 // bond (t, t+1), k_b/2 (|b| - r0)^2: dU/db = k_b (|b| - r0) b/|b|
                 T gsc = kb * (bl - r0);
-                gsc = bvalid ? gsc : (T)0;
+                if constexpr (kMaskFactors) gsc = gsc * mb;
+                else gsc = bvalid ? gsc : (T)0;
                 Dx[t] = gsc * vx; Dy[t] = gsc * vy; Dz[t] = gsc * vz;
                 if (ENERGY && bvalid) e_bond += 0.5 * (double)(kb * (bl - r0) * (bl - r0));
                 // angle centred on slot t between bond a (t-1 -> t) and bond b (t -> t+1),
@@ -215,8 +232,13 @@ struct ChainForce {
             // bead the previous lane's slot B+1 (force -D_B there)
             const T lx = pull_f(next, Dx[0]), ly = pull_f(next, Dy[0]), lz = pull_f(next, Dz[0]);
             const T fx0 = pull_f(prev, Dx[B]), fy0 = pull_f(prev, Dy[B]), fz0 = pull_f(prev, Dz[B]);
-            if (g + 1 < G) { fx[B - 1] += lx; fy[B - 1] += ly; fz[B - 1] += lz; }
-            if (g > 0) { fx[0] -= fx0; fy[0] -= fy0; fz[0] -= fz0; }
+            if constexpr (kMaskFactors) {
+                fx[B - 1] += lx * m_next; fy[B - 1] += ly * m_next; fz[B - 1] += lz * m_next;
+                fx[0] -= fx0 * m_prev; fy[0] -= fy0 * m_prev; fz[0] -= fz0 * m_prev;
+            } else {
+                if (g + 1 < G) { fx[B - 1] += lx; fy[B - 1] += ly; fz[B - 1] += lz; }
+                if (g > 0) { fx[0] -= fx0; fy[0] -= fy0; fz[0] -= fz0; }
+            }
         }
 
         // ---- restraint k/2 (xi - centre)^2 on the pulled end ----
