@@ -41,11 +41,11 @@ FP64_PEAK = 78.6e12
 # 2), which reads the state the first one wrote, as every timed launch does.
 # A record holds only while the kernel sources hash to the digest it was taken on.
 TRAFFIC = {
-    "chain256": {"sources_sha1": "d08e814b0cf2187d0dcd2d50a9459d5cd398f8e8", "kernel": "sim_chain<float,64,4>",
-                 "fetch_kib": 517151.0, "fetch_scale": 1048576 / 524316.75, "write_kib": 1028608.0,
+    "chain256": {"sources_sha1": "132d8b7818ff4fe038531f59df1060b7b3448968", "kernel": "sim_chain<float,64,4>",
+                 "fetch_kib": 517151.0, "fetch_scale": 1048576 / 524315.9375, "write_kib": 1028608.0,
                  "write_scale": 1048576 / 1048576.0},
-    "chain10": {"sources_sha1": "d08e814b0cf2187d0dcd2d50a9459d5cd398f8e8", "kernel": "sim_chain<float,5,2>",
-                "fetch_kib": 169.5, "fetch_scale": 1048576 / 524309.25, "write_kib": 10145.71875,
+    "chain10": {"sources_sha1": "132d8b7818ff4fe038531f59df1060b7b3448968", "kernel": "sim_chain<float,5,2>",
+                "fetch_kib": 169.0, "fetch_scale": 1048576 / 524308.125, "write_kib": 10145.71875,
                 "write_scale": 1048576 / 1048576.0},
 }
 KERNEL_SOURCES = ("ppp_sim_impl.hpp", "ppp_chain_force.hpp", "ppp_device.hpp", "ppp_internal.hpp", "ppp_sim.hip",

@@ -15,13 +15,14 @@ struct ChainForce {
     // groups of at most 6 lanes run no Newton-3 rounds beyond round 2
     static constexpr bool kHaloFromRound1 = G > 1 && (G - 1) / 2 <= 2;
     // Small groups of two-bead lanes (5x2, 6x2), where the bonded terms are a
-    // sixth of the step, mask the bonds beyond the chain's ends and the halo
-    // forces of the group's edge lanes with 0/1 factors instead of selects: a
-    // select reads a lane mask from scalar registers and issues at about half
-    // the rate of a vector-register multiply or FMA, and an add followed by a
-    // select becomes one FMA.  Multiplying by 1 is exact, so the forces are the
-    // same.  The factors stay in vector registers for the whole loop, which the
-    // kernels compiled for more waves per SIMD cannot spare.
+    // sixth of the step, mask the bonds beyond the chain's ends, the halo
+    // forces of the group's edge lanes and the closing half-kick of the fixed
+    // bead with 0/1 factors instead of selects: a select reads a lane mask
+    // from scalar registers and issues at about half the rate of a
+    // vector-register multiply or FMA, and an add followed by a select becomes
+    // one FMA.  Multiplying by 1 is exact, so the results are the same.  The
+    // factors stay in vector registers for the whole loop, which the kernels
+    // compiled for more waves per SIMD cannot spare.
     static constexpr bool kMaskFactors = G > 1 && G <= 6 && B == 2;
 
     // Lennard-Jones between bead sets a (owned) and b; N3: also accumulate reaction on b.
@@ -308,10 +309,21 @@ __device__ __forceinline__ void baoab_step(const DevProblem &P, int g, int gbase
         }
     });
     ChainForce<T, G, B, false>::compute(P, g, gbase, centre, kr, px, py, pz, fx, fy, fz, nullptr);
+    if constexpr (ChainForce<T, G, B, false>::kMaskFactors) {
+        // the closing half-kick with a zero factor for the fixed bead and the
+        // padding (no select; the mobile beads' kick is the same FMA)
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int i = i0 + b;
-        if (i > 0 && i < N) { vx[b] += hm * fx[b]; vy[b] += hm * fy[b]; vz[b] += hm * fz[b]; }
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            const T hmb = (i > 0 && i < N) ? hm : (T)0;
+            vx[b] += hmb * fx[b]; vy[b] += hmb * fy[b]; vz[b] += hmb * fz[b];
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int i = i0 + b;
+            if (i > 0 && i < N) { vx[b] += hm * fx[b]; vy[b] += hm * fy[b]; vz[b] += hm * fz[b]; }
+        }
     }
 }
 
